@@ -1,0 +1,234 @@
+"""Benchmark of the lattice-kinetic Poisson sweep on one MI355X.
+
+Workload (one GPU): periodic 1024 x 1024 grid, higher-order scheme at order
+N = 5 on D2Q81, Kn = 0.1 (tau_lb = 118.26), FP64, source = 64 Gaussians of
+width 2 cells with N(0,1) amplitudes at seeded uniform positions, mean removed.
+
+A step is one pass of the solver's hot path: one chunk of --chunk sweeps
+(fused pull-stream / moment / collide+source), the FP64 convergence
+reductions on the last two sweeps, the read-back of the norms and the host's
+stopping decision.  Inputs are resident in HBM before timing starts.
+
+Printed: one JSON line with GLUPS (cell updates per second; one update moves
+all Q populations of a cell), the roofline of the sweep kernel from HIP events
+on the solver's stream, the oracle's CPU throughput on a bounded sample, and
+extra measurements (other orders, FP32, 3D, time-to-solution).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+ORDERS = {1: "D2Q25", 3: "D2Q25", 5: "D2Q81", 7: "D2Q169"}
+
+
+def bytes_per_cell(Q: int, precision: str) -> int:
+    """Algorithmic HBM bytes of one sweep per cell (pull, two buffers):
+    read Q populations + write Q populations + read S."""
+    b = 8 if precision == "f64" else 4
+    return 2 * b * Q + b
+
+
+def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=None,
+               sweeps=200, chunks=1):
+    """Average duration of one sweep (HIP events on the solver's stream)."""
+    with lkp.Problem(s, lattice, order, knudsen=knudsen, tau_lb=tau_lb, precision=precision) as p:
+        p.step(2)
+        p.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(chunks):
+            p.step(sweeps)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / (sweeps * chunks)
+        info = p.info()
+    n = int(np.prod(s.shape))
+    bpc = bytes_per_cell(info["Q"], precision)
+    return {"lattice": lattice, "order": order, "precision": precision,
+            "ms_per_sweep": ms, "glups": n / (ms * 1e-3) / 1e9,
+            "gbs": n * bpc / (ms * 1e-3) / 1e9,
+            "frac_hbm": n * bpc / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "velocity_groups": info["velocity_groups"], "tau_lb": info["tau_lb"]}
+
+
+KERNEL_SOURCES = ["paper_1504_05869_amd/csrc/sweep_impl.hpp", "paper_1504_05869_amd/csrc/lattices.hpp",
+                  "paper_1504_05869_amd/csrc/kernels.hpp", "paper_1504_05869_amd/csrc/device_common.hpp"]
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{tag}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return int(round(rec["traffic_bytes"]))
+
+
+def cpu_baseline(s, lattice, order, tau, seconds=15.0):
+    """Oracle C sweep (FP64, OpenMP) on the same grid for a bounded time."""
+    from oracle import sweep as SW
+    prob = SW.Problem(lattice, order, tau, s)
+    a = prob.zero_state()
+    b = np.empty_like(a)
+    Phi = np.empty(s.shape)
+    SW.sweep_c(prob, a, b, Phi)                 # warm (page in)
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds or k < 2:
+        SW.sweep_c(prob, a, b, Phi)
+        a, b = b, a
+        k += 1
+    dt = time.perf_counter() - t0
+    return {"value": s.size * k / dt / 1e9, "unit": "GLUPS", "cores": SW.threads(),
+            "kind": "oracle",
+            "sample": f"{k} full sweeps of the {s.shape[1]}x{s.shape[0]} {lattice} N={order} "
+                      f"FP64 grid in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chunk", type=int, default=100, help="sweeps per step")
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the sweep of a single problem runs on one device).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1504_05869_amd as lkp
+    from paper_1504_05869_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    shape = (1024, 1024)
+    lattice, order, kn, precision = "D2Q81", 5, 0.1, "f64"
+    s = W.poisson_source("blobs2d", shape, seed=12345)
+    n = s.size
+
+    if args.calibrate_copy:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    p = lkp.Problem(s, lattice, order, knudsen=kn, precision=precision)
+    info = p.info()
+    Q = info["Q"]
+
+    def step():
+        # one chunk with the convergence check; the unreachable tolerance keeps
+        # the solver going, so each call does exactly `chunk` sweeps
+        return p.solve(tol_rel_l2=1e-300, max_sweeps=args.chunk, check_every=args.chunk,
+                       use_graph=True, raise_on_error=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    last = None
+    for _ in range(args.steps):
+        last = step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweeps = args.steps * args.chunk
+    glups = n * sweeps / wall / 1e9
+    # sweep kernel duration: events around plain sweeps on the same stream
+    p.sync()
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record()
+    p.step(args.chunk * 5)
+    k1.record()
+    k1.synchronize()
+    ms_sweep = k0.elapsed_time(k1) / (args.chunk * 5)
+    p.close()
+    bpc = bytes_per_cell(Q, precision)
+    achieved = n * bpc / (ms_sweep * 1e-3) / 1e9
+
+    out = {
+        "metric": "GLUPS (lattice cell updates per second, all Q populations per update)",
+        "value": round(glups, 4),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D periodic 1024x1024 Poisson, D2Q81 N=5, Kn=0.1 "
+                               f"(tau_lb={info['tau_lb']:.4f}), 64 Gaussians sigma=2, FP64",
+                   "grid": [1024, 1024], "lattice": lattice, "order": order, "knudsen": kn,
+                   "sweeps_per_step": args.chunk, "velocity_groups": info["velocity_groups"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("k_sweep_d2q81_f64_1024x1024"),
+                     "kernel": "k_sweep (D2Q81, FP64)",
+                     "bytes_per_launch": n * bpc, "ms_per_launch": round(ms_sweep, 5)},
+        "last_check": {"est_rel_err": last["est_rel_err"], "rate": last["rate"]},
+    }
+
+    if not args.no_extras:
+        extras = []
+        for N, lat in ORDERS.items():
+            for prec in ("f64", "f32"):
+                r = sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200)
+                extras.append(r)
+        s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
+        for prec in ("f32", "f64"):
+            extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
+                                          sweeps=40), grid="256^3"))
+        del s3
+        out["sweeps"] = [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in e.items()}
+                         for e in extras]
+        # time-to-solution on the headline problem, FP64 and FP32 + refinement
+        tts = []
+        for prec, tol in (("f64", 1e-10), ("f32_ir", 1e-10), ("f32_ir", 1e-6)):
+            with lkp.Problem(s, lattice, order, knudsen=kn, precision=prec) as q:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                rep = q.solve(tol_rel_l2=tol, check_every=100, max_sweeps=2_000_000)
+                torch.cuda.synchronize()
+                tts.append({"precision": prec, "tol_rel_l2": tol,
+                            "seconds": round(time.perf_counter() - t1, 4),
+                            "sweeps": rep["sweeps"], "outer": rep["outer"],
+                            "est_rel_err": rep["est_rel_err"]})
+        out["time_to_solution"] = tts
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(s, lattice, order, info["tau_lb"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * lkp -- higher-order lattice-kinetic Poisson solver for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Mendoza, Succi, Herrmann, "High-Order Kinetic Relaxation Schemes as
+ * High-Accuracy Poisson Solvers".  A periodic Poisson problem lap(Phi) = -s
+ * is solved as the steady state of the diffusion equation with source
+ * (Sec. 2, Eq. DIFFU), itself the small-Knudsen limit of a BGK kinetic equation
+ * (Eq. boltzmann).  On a lattice of Q discrete velocities v_i each sweep does,
+ * for every cell x (Sec. 3 and 4):
+ *
+ *     stream (pull):    f_i(x)    = f*_i(x - v_i)              (periodic)
+ *     moment:           Phi(x)    = sum_i f_i(x)
+ *     collide + source: f*_i'(x)  = (1 - omega) f_i(x) + omega phi_i Phi(x) + chi_i S(x)
+ *
+ * with omega = 1 / tau_lb, the separable equilibrium phi(v) Phi (Eq. equilibrium2)
+ * and source chi(v) S whose Hermite coefficients cancel the unwanted moments up
+ * to order N (Eq. CON; Eqs. omega:eq, chi:eq, omega:eq3, chi:eq3), and the
+ * strong source S = s c_s^2 (tau_lb - 1/2) (Sec. 4).  The answer is Phi at the
+ * fixed point of the sweep.
+ *
+ * Conventions for every call:
+ *  - Fields are periodic, stored x fastest: index (z * ny + y) * nx + x.
+ *    Population state is Q planes of n = nx*ny*nz cells ("SoA"), plane i
+ *    holding velocity i of lkp_lattice_info's table.
+ *  - All calls return lkp_status (LKP_OK = 0); no exception crosses the ABI.
+ *    lkp_last_error() gives a thread-local message for the last failure.
+ *  - Device pointers are HIP device pointers valid on the handle's device;
+ *    "host" pointers are ordinary process memory.
+ *  - A handle is not thread-safe; all its GPU work is enqueued on the stream
+ *    given at creation (NULL = the default stream).  Calls that return data
+ *    to the host synchronise that stream.
+ */
+#ifndef LKP_H
+#define LKP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lkp_status {
+  LKP_OK = 0,
+  LKP_ERR_ARG = 1,            /* invalid argument (shape, pointer, option) */
+  LKP_ERR_LATTICE_ORDER = 2,  /* order N not 1/3/5/7, or above the set's maximum, or dim mismatch */
+  LKP_ERR_UNSTABLE = 3,       /* tau_lb below the set/order stability limit */
+  LKP_ERR_SOURCE_MEAN = 4,    /* |mean(s)| > 1e-12 max|s| and subtract_mean == 0 */
+  LKP_ERR_OOM = 5,            /* device allocation failed */
+  LKP_ERR_HIP = 6,            /* a HIP runtime call failed */
+  LKP_ERR_NOT_CONVERGED = 7,  /* lkp_solve reached max_sweeps */
+  LKP_ERR_DIVERGED = 8,       /* non-finite values or sustained growth */
+  LKP_ERR_STATE = 9,          /* call not valid in the handle's current state */
+  LKP_ERR_UNSUPPORTED = 10    /* combination not built (e.g. lattice/precision) */
+} lkp_status;
+
+/* Velocity sets.  1D sets: Appendix A.  2D: tensor products of the 1D sets
+ * (the paper's "tensorial" extension, Sec. 3) and the standard
+ * nearest-neighbour D2Q5 / D2Q9.  3D: D3Q111 (Appendix A, Table vector2). */
+typedef enum lkp_lattice {
+  LKP_D1Q5 = 0,   /* N <= 3 */
+  LKP_D1Q9 = 1,   /* N <= 5 */
+  LKP_D1Q13 = 2,  /* N <= 7 */
+  LKP_D2Q5 = 3,   /* N = 1, standard LB */
+  LKP_D2Q9 = 4,   /* N <= 3 */
+  LKP_D2Q25 = 5,  /* N <= 3 */
+  LKP_D2Q81 = 6,  /* N <= 5 */
+  LKP_D2Q169 = 7, /* N <= 7 */
+  LKP_D3Q111 = 8, /* N <= 5 */
+  LKP_NUM_LATTICES = 9
+} lkp_lattice;
+
+typedef enum lkp_precision {
+  LKP_F64 = 0,    /* FP64 populations, FP64 everything */
+  LKP_F32 = 1,    /* FP32 populations and sweep (FP64 moment sum and norms), no refinement */
+  LKP_F32_IR = 2  /* FP32 inner sweeps inside FP64 iterative refinement on the population state */
+} lkp_precision;
+
+typedef struct lkp_problem_desc {
+  int32_t dim;              /* 1, 2 or 3; must equal the lattice's dimension */
+  int32_t lattice;          /* lkp_lattice */
+  int64_t n[3];             /* nx, ny, nz; axes beyond dim must be 1; each >= 1;
+                               nx*ny*nz < 2^31 */
+  int32_t order;            /* expansion order N: 1, 3, 5 or 7 (Sec. 3) */
+  int32_t precision;        /* lkp_precision */
+  double tau_lb;            /* lattice relaxation time; used when knudsen <= 0 */
+  double knudsen;           /* > 0: tau_lb = 1/2 + Kn * L / c_s, L = smallest box side
+                               (Kn = lambda / L, Sec. 2, with lambda = c_s (tau_lb - 1/2)) */
+  const double *source;     /* s in lap(Phi) = -s (Sec. 4, Eq. poisson1: s = rho/eps),
+                               nx*ny*nz FP64 values; copied at creation, the caller
+                               keeps ownership */
+  int32_t source_on_device; /* 1: `source` is a device pointer */
+  int32_t subtract_mean;    /* 1: remove the mean of s instead of rejecting it */
+  int32_t allow_unstable;   /* 1: skip the tau_lb stability check */
+  int32_t reserved;
+  void *stream;             /* hipStream_t for all of this handle's work; NULL = default */
+} lkp_problem_desc;
+
+typedef struct lkp_handle lkp_handle;
+
+/* Create a problem: validates the description, computes the set's weights,
+ * c_s^2, phi_i, chi_i (long double, rounded once), scales the source
+ * S = s c_s^2 (tau_lb - 1/2), allocates the device state (two population
+ * buffers, S, Phi buffers, reduction scratch) and sets f* = 0.
+ * Ownership: the handle owns all device memory it allocates; release with
+ * lkp_destroy.  Errors: LKP_ERR_ARG, LKP_ERR_LATTICE_ORDER, LKP_ERR_UNSTABLE,
+ * LKP_ERR_SOURCE_MEAN, LKP_ERR_OOM, LKP_ERR_HIP; *out is NULL on failure. */
+lkp_status lkp_create(const lkp_problem_desc *d, lkp_handle **out);
+
+/* Release every resource of the handle (NULL is accepted). */
+lkp_status lkp_destroy(lkp_handle *h);
+
+/* Device bytes lkp_create would allocate for `d` (0 if `d` is invalid). */
+int64_t lkp_footprint_bytes(const lkp_problem_desc *d);
+
+typedef struct lkp_solve_opts {
+  double tol_rel_l2;    /* > 0: stop when the estimated relative L2 distance of Phi to the
+                           fixed point, |dPhi| rho / (1 - rho) / |Phi| with rho the measured
+                           per-sweep contraction, is <= tol_rel_l2 */
+  double tol_maxchange; /* > 0: stop when max_x |Phi_t - Phi_{t-1}| < tol_maxchange */
+  int64_t max_sweeps;   /* hard cap on sweeps done by this call (> 0) */
+  int32_t check_every;  /* sweeps between convergence checks (>= 1) */
+  int32_t max_outer;    /* LKP_F32_IR: cap on refinement steps (0 = 20) */
+  double ir_inner_tol;  /* LKP_F32_IR: relative reduction of the correction per inner
+                           solve (0 = 1e-4) */
+  int32_t use_graph;    /* 1: replay the chunk of sweeps as a captured hipGraph */
+  int32_t reserved;
+} lkp_solve_opts;
+
+typedef struct lkp_solve_report {
+  int64_t sweeps;        /* sweeps done by this call (inner sweeps for F32_IR) */
+  int64_t total_sweeps;  /* sweeps since creation */
+  int32_t outer;         /* refinement steps (F32_IR) */
+  int32_t status;        /* same as the return value */
+  double max_change;     /* max |Phi_t - Phi_{t-1}| at the last check */
+  double l2_change;      /* ||Phi_t - Phi_{t-1}||_2 at the last check */
+  double phi_l2;         /* ||Phi||_2 */
+  double mass;           /* sum_x Phi */
+  double est_rel_err;    /* estimated relative L2 distance to the fixed point */
+  double rate;           /* measured per-sweep contraction rho */
+  double wall_s;         /* wall time of the call */
+  double glups;          /* 1e-9 * cells * sweeps / wall_s */
+} lkp_solve_report;
+
+/* Sweep until the stopping rule of `o` holds (Sec. 4: the steady state of the
+ * iteration is the Poisson solution).  The convergence norms are FP64
+ * wavefront reductions on the GPU, read back once per check.  The state stays
+ * resident, so a later call resumes.  Returns LKP_ERR_NOT_CONVERGED at
+ * max_sweeps, LKP_ERR_DIVERGED on non-finite values or growth.  `rep` may be
+ * NULL. */
+lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *rep);
+
+/* Advance exactly `sweeps` sweeps (>= 0).  The last sweep stores Phi. */
+lkp_status lkp_step(lkp_handle *h, int64_t sweeps);
+
+typedef struct lkp_residual_report {
+  double max_change;      /* max |Phi_{t+1} - Phi_t|: one-sweep change of the moment, the
+                             discrete Poisson residual in the scheme's own units */
+  double l2_change;       /* ||Phi_{t+1} - Phi_t||_2 */
+  double pop_residual_l2; /* ||T f* + g - f*||_2 over all populations (FP64) */
+  double phi_l2;          /* ||Phi_t||_2 */
+  double mass;            /* sum_x Phi_t */
+  int64_t sweeps;         /* sweeps since creation */
+} lkp_residual_report;
+
+/* Residual of the current state in FP64 on the GPU, without advancing it
+ * (needs at least one sweep done: LKP_ERR_STATE otherwise). */
+lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r);
+
+/* Phi of the last sweep (post-stream moment, Sec. 2: Phi = sum_i f_i), n FP64
+ * values into caller-owned memory.  LKP_ERR_STATE before the first sweep or
+ * after lkp_set_populations. */
+lkp_status lkp_get_phi(lkp_handle *h, double *dst, int32_t dst_is_device);
+
+/* Copy the post-collision population state (Q*n FP64, plane-major, plane i =
+ * velocity i) out of / into the handle; FP32 states are converted. */
+lkp_status lkp_get_populations(lkp_handle *h, double *dst, int32_t dst_is_device);
+lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_device);
+
+/* Constants of a set at order N (host memory, caller-owned; any pointer may be
+ * NULL): Q, dim, velocities v[Q][3], weights w, phi_i, chi_i and c_s^2.  Arrays
+ * must hold at least 169 (x3 for v) entries. */
+lkp_status lkp_lattice_info(int32_t lattice, int32_t order, int32_t *Q, int32_t *dim,
+                            int32_t *v, double *w, double *phi, double *chi, double *cs2);
+
+typedef struct lkp_handle_info {
+  int32_t lattice, order, dim, Q, precision, velocity_groups;
+  int64_t n[3];
+  double tau_lb, omega, cs2;
+  int64_t total_sweeps;
+  int64_t footprint_bytes;
+} lkp_handle_info;
+
+lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info);
+
+/* Wait for all of the handle's queued work. */
+lkp_status lkp_sync(lkp_handle *h);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *lkp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LKP_H */

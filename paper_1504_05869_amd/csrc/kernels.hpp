@@ -1,0 +1,98 @@
+// Launch interface of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattices.hpp"
+
+namespace lkp {
+
+// Precision modes of the fused sweep.
+enum SweepMode : int {
+  MODE_F64 = 0,    // FP64 in, FP64 out, source chi_i S(x)
+  MODE_F32 = 1,    // FP32 in, FP32 out, source chi_i S(x) (S in FP32); FP64 moment sum
+  MODE_RESID = 2,  // FP64 in, FP32 out r_i = (T x + g)_i - x_i, FP64 arithmetic
+  MODE_INNER = 3,  // FP32 in, FP32 out, population-space source r_i(x) (Q FP32 planes)
+  NUM_MODES = 4
+};
+
+// Extra work of one sweep.
+enum SweepFlags : int {
+  FLAG_PHI = 1,     // store Phi (FP64)
+  FLAG_REDUCE = 2,  // also per-block partial norms (implies FLAG_PHI)
+};
+
+// Partial-norm slots, per block and in the finished result.
+enum NormSlot : int {
+  NORM_MAX_DPHI = 0,  // max |Phi - Phi_prev|
+  NORM_SUM_DPHI2 = 1, // sum (Phi - Phi_prev)^2
+  NORM_SUM_PHI2 = 2,  // sum Phi^2
+  NORM_SUM_PHI = 3,   // sum Phi
+  NORM_BAD = 4,       // count of non-finite Phi / residual values
+  NORM_SUM_R2 = 5,    // sum over populations of r_i^2 (MODE_RESID)
+  NUM_NORMS = 6
+};
+
+struct SweepParams {
+  const void *fin;        // Q planes, input precision of the mode
+  void *fout;             // Q planes, output precision of the mode
+  const void *src;        // S (n values) or r (Q planes) in the mode's source precision
+  const void *coef;       // compute precision: [omega phi_i]_Q, [chi_i]_Q
+  double om1;             // 1 - omega
+  const double *phi_prev; // previous sweep's Phi (FLAG_REDUCE; may be null)
+  double *phi_out;        // this sweep's Phi (FLAG_PHI)
+  double *partials;       // NUM_NORMS per block (FLAG_REDUCE)
+  unsigned nx, ny, nz;
+  unsigned ncells;        // nx * ny * nz (< 2^31)
+  unsigned simple_wrap;   // 1 when every axis is at least its largest |v| component
+  unsigned nblocks;       // grid size (set by the launcher)
+};
+
+// Cells one block covers for a velocity-group split P (256 threads = 4 waves;
+// P waves share one 64-cell column and each holds Q/P populations).
+inline unsigned cells_per_block(int P) { return 256u / (unsigned)P; }
+
+// Velocity-group splits compiled per (lattice, mode): small sets P = 1; for
+// the large ones the candidates the tuner chooses between.
+constexpr bool sweep_variant_built(int lattice, int mode, int P) {
+  const int q = velocity_table(lattice).q;
+  const bool wide = (mode == MODE_F64 || mode == MODE_RESID);
+  if (q <= 25) return P == 1;
+  if (mode == MODE_RESID) return P == (q >= 169 ? 4 : 2);
+  if (mode == MODE_INNER) return P == (q >= 169 ? 2 : 1);
+  if (wide) {
+    if (q <= 81) return P == 1 || P == 2;
+    return P == 2 || P == 4;
+  }
+  if (q <= 81) return P == 1;
+  return P == 1 || P == 2;
+}
+
+// Whether a (lattice, mode, P) variant is compiled.
+bool sweep_variant_available(int lattice, int mode, int P);
+
+// Per-lattice entry points, one translation unit each (sweep_<lattice>.hip).
+template <int LID>
+hipError_t launch_lattice_tu(int mode, int P, int flags, SweepParams p, hipStream_t s);
+
+// Enqueue one sweep; fills p.nblocks.  Returns hipErrorInvalidValue for an
+// unbuilt variant.
+hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, hipStream_t s);
+
+// Deterministic finish of per-block partials into out[NUM_NORMS] (device).
+hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, hipStream_t s);
+
+// Elementwise helpers.
+hipError_t launch_f64_to_f32(const double *in, float *out, size_t n, hipStream_t s);
+hipError_t launch_f32_to_f64(const float *in, double *out, size_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
+// partials[NUM_NORMS * blocks] (blocks <= max_blocks, the buffer's capacity):
+// slot NORM_SUM_PHI gets the sum of d over all n values.
+hipError_t launch_sum_f32(const float *d, size_t n, double *partials, unsigned max_blocks,
+                          unsigned *nblocks_out, hipStream_t s);
+// x_i(c) += d_i(c) - phi_i * mean, mean = sums[NORM_SUM_PHI] / ncells  (mass-mode projection)
+hipError_t launch_ir_update(double *x, const float *d, const double *phi, const double *sums,
+                            unsigned Q, unsigned ncells, hipStream_t s);
+
+}  // namespace lkp

@@ -1,0 +1,148 @@
+// Discrete velocity sets of the higher-order lattice-kinetic Poisson scheme,
+// as compile-time tables usable in kernels (every index folds to a literal).
+//
+//   1D sets (Appendix A): D1Q5 {0,+-1,+-3} (N <= 3), D1Q9 {0,+-1,+-2,+-3,+-5}
+//     (N <= 5), D1Q13 {0,+-1,...,+-6} (N <= 7).
+//   2D: the paper only says the extension uses tensor Hermite polynomials
+//     (Sec. 3); D2Q25, D2Q81, D2Q169 are tensor products of the 1D sets.
+//     D2Q5 and D2Q9 are the standard nearest-neighbour sets.
+//   3D: D3Q111 (Appendix A, Table vector2), ten shells of signed
+//     permutations, N <= 5.
+#pragma once
+
+namespace lkp {
+
+enum LatticeId : int {
+  D1Q5 = 0, D1Q9, D1Q13, D2Q5, D2Q9, D2Q25, D2Q81, D2Q169, D3Q111, NUM_LATTICES
+};
+
+constexpr int MAXQ = 169;
+
+struct VelTable {
+  int v[MAXQ][3];
+  int q;
+  int dim;
+  int max_order;
+};
+
+namespace detail {
+
+constexpr int S5[5] = {0, 1, -1, 3, -3};
+constexpr int S9[9] = {0, 1, -1, 2, -2, 3, -3, 5, -5};
+constexpr int S13[13] = {0, 1, -1, 2, -2, 3, -3, 4, -4, 5, -5, 6, -6};
+
+constexpr VelTable line(const int* s, int m, int max_order) {
+  VelTable t{};
+  for (int i = 0; i < m; ++i) t.v[i][0] = s[i];
+  t.q = m;
+  t.dim = 1;
+  t.max_order = max_order;
+  return t;
+}
+
+// index i = iy * m + ix, v = (s[ix], s[iy])
+constexpr VelTable square(const int* s, int m, int max_order) {
+  VelTable t{};
+  int k = 0;
+  for (int iy = 0; iy < m; ++iy)
+    for (int ix = 0; ix < m; ++ix) {
+      t.v[k][0] = s[ix];
+      t.v[k][1] = s[iy];
+      ++k;
+    }
+  t.q = k;
+  t.dim = 2;
+  t.max_order = max_order;
+  return t;
+}
+
+constexpr VelTable nearest(bool diagonals) {
+  VelTable t{};
+  const int axis[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+  const int diag[4][2] = {{1, 1}, {-1, 1}, {1, -1}, {-1, -1}};
+  int k = 1;
+  for (int i = 0; i < 4; ++i) { t.v[k][0] = axis[i][0]; t.v[k][1] = axis[i][1]; ++k; }
+  if (diagonals)
+    for (int i = 0; i < 4; ++i) { t.v[k][0] = diag[i][0]; t.v[k][1] = diag[i][1]; ++k; }
+  t.q = k;
+  t.dim = 2;
+  t.max_order = diagonals ? 3 : 1;
+  return t;
+}
+
+// Table vector2 shell representatives, in the table's order.
+constexpr int SHELLS111[10][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {3, 3, 3}, {3, 3, 0},
+                                  {3, 1, 0}, {2, 2, 0}, {2, 1, 1}, {2, 0, 0}, {3, 0, 0}};
+
+constexpr VelTable d3q111() {
+  VelTable t{};
+  const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  int k = 0;
+  for (int s = 0; s < 10; ++s) {
+    const int start = k;
+    for (int p = 0; p < 6; ++p)
+      for (int sg = 0; sg < 8; ++sg) {
+        int c[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {
+          const int val = SHELLS111[s][perm[p][a]];
+          c[a] = ((sg >> a) & 1) ? -val : val;
+        }
+        bool seen = false;
+        for (int j = start; j < k; ++j)
+          if (t.v[j][0] == c[0] && t.v[j][1] == c[1] && t.v[j][2] == c[2]) seen = true;
+        if (!seen) {
+          t.v[k][0] = c[0];
+          t.v[k][1] = c[1];
+          t.v[k][2] = c[2];
+          ++k;
+        }
+      }
+  }
+  t.q = k;
+  t.dim = 3;
+  t.max_order = 5;
+  return t;
+}
+
+}  // namespace detail
+
+constexpr VelTable velocity_table(int id) {
+  switch (id) {
+    case D1Q5: return detail::line(detail::S5, 5, 3);
+    case D1Q9: return detail::line(detail::S9, 9, 5);
+    case D1Q13: return detail::line(detail::S13, 13, 7);
+    case D2Q5: return detail::nearest(false);
+    case D2Q9: return detail::nearest(true);
+    case D2Q25: return detail::square(detail::S5, 5, 3);
+    case D2Q81: return detail::square(detail::S9, 9, 5);
+    case D2Q169: return detail::square(detail::S13, 13, 7);
+    case D3Q111: return detail::d3q111();
+    default: return VelTable{};
+  }
+}
+
+constexpr int max_component(const VelTable& t, int axis) {
+  int m = 0;
+  for (int i = 0; i < t.q; ++i) {
+    const int a = t.v[i][axis] < 0 ? -t.v[i][axis] : t.v[i][axis];
+    if (a > m) m = a;
+  }
+  return m;
+}
+
+// Compile-time view of one set, for kernel templates.
+template <int ID>
+struct Lattice {
+  static constexpr VelTable table = velocity_table(ID);
+  static constexpr int Q = table.q;
+  static constexpr int DIM = table.dim;
+  static constexpr int VMX = max_component(table, 0);
+  static constexpr int VMY = max_component(table, 1);
+  static constexpr int VMZ = max_component(table, 2);
+};
+
+static_assert(velocity_table(D3Q111).q == 111, "Table vector2 lists 111 velocities");
+static_assert(velocity_table(D2Q169).q == 169, "");
+static_assert(velocity_table(D2Q81).q == 81, "");
+
+}  // namespace lkp

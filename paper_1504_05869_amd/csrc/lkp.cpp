@@ -1,0 +1,889 @@
+// C-ABI runtime of the lattice-kinetic Poisson solver (see include/lkp.h).
+//
+// Host side only: validation, constants, device memory, the chunked
+// convergence loop (sweeps, FP64 norms, one small read-back per chunk),
+// hipGraph replay of chunks, the velocity-group tuner and the FP64
+// iterative-refinement controller around FP32 inner sweeps.
+#include "lkp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "constants.hpp"
+#include "kernels.hpp"
+
+using namespace lkp;
+
+namespace {
+
+thread_local std::string g_err;
+
+lkp_status fail(lkp_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? LKP_ERR_OOM : LKP_ERR_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                     \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Process-wide choice of the velocity-group split per (lattice, mode, size class).
+std::mutex g_tune_mu;
+std::map<long, int> g_tune;
+
+long tune_key(int lattice, int mode, int64_t ncells) {
+  int cls = 0;
+  while ((int64_t(1) << (2 * cls + 12)) < ncells && cls < 12) ++cls;
+  return ((long)lattice * 16 + mode) * 32 + cls;
+}
+
+int default_split(int Q, int mode) {
+  const bool wide = (mode == MODE_F64 || mode == MODE_RESID);
+  if (Q <= 25) return 1;
+  if (wide) return Q >= 169 ? 4 : 2;
+  return Q >= 169 ? 2 : 1;
+}
+
+}  // namespace
+
+struct lkp_handle {
+  int lattice = 0, order = 0, dim = 0, precision = 0, Q = 0;
+  int64_t n[3] = {1, 1, 1};
+  unsigned ncells = 0;
+  double tau_lb = 0, omega = 0, cs2 = 0;
+  std::vector<double> w, phi, chi;
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;  // private stream used only to record graphs
+  bool simple_wrap = true;
+
+  // population state: F64 -> f[] double; F32 -> f[] float; F32_IR -> x (double) + d[] float
+  void *f[2] = {nullptr, nullptr};
+  int cur = 0;
+  void *S = nullptr;        // scaled source in the sweep precision (double for IR)
+  void *coef = nullptr;     // sweep precision coefficients
+  void *coef32 = nullptr;   // IR inner coefficients (float)
+  double *phi_dev = nullptr;  // phi_i on device (IR mass projection)
+  float *r32 = nullptr;       // IR residual
+  float *d32[2] = {nullptr, nullptr};
+  double *phib[2] = {nullptr, nullptr};
+  int64_t phi_sweep[2] = {-1, -1};
+  int phi_last = 1;
+  double *partials = nullptr;
+  size_t partial_cap = 0;
+  double *norms_dev = nullptr;
+  double *norms_host = nullptr;  // pinned
+  int64_t total_sweeps = 0;
+  int64_t footprint = 0;
+  int split = 1;
+  bool tuned = false;
+  std::map<long, hipGraphExec_t> graphs;
+
+  int mode() const { return precision == LKP_F64 ? MODE_F64 : MODE_F32; }
+};
+
+namespace {
+
+size_t pop_bytes(const lkp_handle &h) {
+  return (size_t)h.Q * h.ncells * (h.precision == LKP_F64 ? 8 : 4);
+}
+
+int64_t footprint_of(int precision, int Q, int64_t ncells) {
+  const int64_t nb = (ncells + 63) / 64 + 8;
+  int64_t b = 3 * 8 * ncells + nb * NUM_NORMS * 8 + 4096;  // S + 2 Phi + partials + misc
+  if (precision == LKP_F64) b += 2 * 8 * (int64_t)Q * ncells;
+  else if (precision == LKP_F32) b += 2 * 4 * (int64_t)Q * ncells;
+  else b += 8 * (int64_t)Q * ncells + 3 * 4 * (int64_t)Q * ncells;  // x + r + 2 d
+  return b;
+}
+
+lkp_status validate(const lkp_problem_desc *d, LatticeConstants *lc, double *tau_out) {
+  if (!d) return fail(LKP_ERR_ARG, "null problem description");
+  if (d->lattice < 0 || d->lattice >= LKP_NUM_LATTICES)
+    return fail(LKP_ERR_ARG, "unknown lattice %d", d->lattice);
+  const VelTable T = velocity_table(d->lattice);
+  if (d->dim != T.dim)
+    return fail(LKP_ERR_LATTICE_ORDER, "lattice is %dD, problem dim is %d", T.dim, d->dim);
+  if (d->order != 1 && d->order != 3 && d->order != 5 && d->order != 7)
+    return fail(LKP_ERR_LATTICE_ORDER, "order must be 1, 3, 5 or 7 (got %d)", d->order);
+  if (d->order > T.max_order)
+    return fail(LKP_ERR_LATTICE_ORDER, "lattice supports order <= %d (got %d)", T.max_order,
+                d->order);
+  if (d->precision < LKP_F64 || d->precision > LKP_F32_IR)
+    return fail(LKP_ERR_ARG, "unknown precision %d", d->precision);
+  int64_t cells = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (d->n[a] < 1) return fail(LKP_ERR_ARG, "n[%d] = %lld < 1", a, (long long)d->n[a]);
+    if (a >= d->dim && d->n[a] != 1) return fail(LKP_ERR_ARG, "n[%d] must be 1 for dim %d", a, d->dim);
+    cells *= d->n[a];
+    if (cells >= (int64_t(1) << 31)) return fail(LKP_ERR_ARG, "grid too large (>= 2^31 cells)");
+  }
+  if (!lattice_constants(d->lattice, lc)) return fail(LKP_ERR_HIP, "lattice constant solve failed");
+  double tau = d->tau_lb;
+  if (d->knudsen > 0) {
+    int64_t L = d->n[0];
+    for (int a = 1; a < d->dim; ++a) L = std::min(L, d->n[a]);
+    tau = 0.5 + d->knudsen * (double)L / std::sqrt((double)lc->cs2);
+  }
+  if (!(tau > 0.5) || !std::isfinite(tau))
+    return fail(LKP_ERR_UNSTABLE, "tau_lb = %g must exceed 1/2", tau);
+  const double thr = stability_threshold(d->lattice, d->order);
+  if (!d->allow_unstable && tau < thr)
+    return fail(LKP_ERR_UNSTABLE, "tau_lb = %g is below the stability limit %g for order %d", tau,
+                thr, d->order);
+  *tau_out = tau;
+  return LKP_OK;
+}
+
+lkp_status ensure_partials(lkp_handle *h, size_t nblocks) {
+  if (nblocks <= h->partial_cap) return LKP_OK;
+  if (h->partials) HIP_TRY(hipFree(h->partials));
+  h->partials = nullptr;
+  HIP_TRY(hipMalloc(&h->partials, nblocks * NUM_NORMS * sizeof(double)));
+  h->partial_cap = nblocks;
+  return LKP_OK;
+}
+
+SweepParams base_params(const lkp_handle *h) {
+  SweepParams p{};
+  p.om1 = 1.0 - h->omega;
+  p.nx = (unsigned)h->n[0];
+  p.ny = (unsigned)h->n[1];
+  p.nz = (unsigned)h->n[2];
+  p.ncells = h->ncells;
+  p.simple_wrap = h->simple_wrap ? 1u : 0u;
+  return p;
+}
+
+// One population sweep of the handle's own state (F64 / F32) from buffer
+// `in` to buffer `out` with `flags`.
+lkp_status enqueue_sweep(lkp_handle *h, hipStream_t s, int in, int out, int flags,
+                         const double *phi_prev, double *phi_out) {
+  SweepParams p = base_params(h);
+  p.fin = h->f[in];
+  p.fout = h->f[out];
+  p.src = h->S;
+  p.coef = h->coef;
+  p.phi_prev = phi_prev;
+  p.phi_out = phi_out;
+  p.partials = h->partials;
+  hipError_t e = launch_sweep(h->lattice, h->mode(), h->split, flags, p, s);
+  if (e != hipSuccess) return fail(LKP_ERR_HIP, "sweep launch: %s", hipGetErrorString(e));
+  return LKP_OK;
+}
+
+lkp_status read_norms(lkp_handle *h, unsigned nblocks, double out[NUM_NORMS]) {
+  hipError_t e = launch_finish(h->partials, nblocks, h->norms_dev, h->stream);
+  if (e != hipSuccess) return fail(LKP_ERR_HIP, "finish launch: %s", hipGetErrorString(e));
+  HIP_TRY(hipMemcpyAsync(h->norms_host, h->norms_dev, NUM_NORMS * sizeof(double),
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  std::memcpy(out, h->norms_host, NUM_NORMS * sizeof(double));
+  return LKP_OK;
+}
+
+unsigned sweep_blocks(const lkp_handle *h, int P) {
+  const unsigned c = cells_per_block(P);
+  return (h->ncells + c - 1) / c;
+}
+
+// Enqueue a chunk of k >= 1 sweeps whose last sweep reduces norms (and, for
+// k >= 2, compares with the sweep before it).  Updates cur / phi bookkeeping.
+lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
+  int cur = h->cur;
+  for (int j = 0; j < k - 2; ++j) {
+    if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, 0, nullptr, nullptr)) return st;
+    cur = 1 - cur;
+  }
+  if (k >= 2) {
+    if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, FLAG_PHI, nullptr, h->phib[0])) return st;
+    cur = 1 - cur;
+    if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, FLAG_REDUCE, h->phib[0], h->phib[1]))
+      return st;
+    cur = 1 - cur;
+  } else {
+    const int a = h->phi_last, b = 1 - h->phi_last;
+    if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, FLAG_REDUCE, h->phib[a], h->phib[b]))
+      return st;
+    cur = 1 - cur;
+  }
+  return LKP_OK;
+}
+
+void commit_chunk(lkp_handle *h, int k) {
+  const int64_t t0 = h->total_sweeps;
+  if (k % 2) h->cur = 1 - h->cur;
+  if (k >= 2) {
+    h->phi_sweep[0] = t0 + k - 1;
+    h->phi_sweep[1] = t0 + k;
+    h->phi_last = 1;
+  } else {
+    h->phi_last = 1 - h->phi_last;
+    h->phi_sweep[h->phi_last] = t0 + 1;
+  }
+  h->total_sweeps = t0 + k;
+}
+
+lkp_status run_chunk(lkp_handle *h, int k, bool use_graph) {
+  if (use_graph && k >= 2) {
+    const long key = (long)k * 2 + h->cur;
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+      if (!h->capture) HIP_TRY(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+      lkp_status st = enqueue_chunk(h, h->capture, k);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(h->capture, &g);
+      if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(LKP_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(LKP_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+      it = h->graphs.emplace(key, ex).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, h->stream));
+  } else {
+    if (lkp_status st = enqueue_chunk(h, h->stream, k)) return st;
+  }
+  commit_chunk(h, k);
+  return LKP_OK;
+}
+
+void drop_graphs(lkp_handle *h) {
+  for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+}
+
+// Pick the velocity-group split by timing each built candidate on the
+// handle's own buffers.  Sweeps read f[cur] and write f[1-cur] without
+// swapping, so the state is unchanged.
+lkp_status tune_split(lkp_handle *h) {
+  if (h->tuned) return LKP_OK;
+  h->tuned = true;
+  const int mode = h->precision == LKP_F32_IR ? MODE_INNER : h->mode();
+  const long key = tune_key(h->lattice, mode, h->ncells);
+  // LKP_SPLIT forces a split when that variant is built (tests, experiments)
+  if (const char *env = std::getenv("LKP_SPLIT")) {
+    const int P = std::atoi(env);
+    if (sweep_variant_available(h->lattice, mode, P)) {
+      h->split = P;
+      return LKP_OK;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      h->split = it->second;
+      return LKP_OK;
+    }
+  }
+  const char *off = std::getenv("LKP_AUTOTUNE");
+  if ((off && std::atoi(off) == 0) || h->ncells < 4096 || h->precision == LKP_F32_IR) {
+    h->split = default_split(h->Q, mode);
+    return LKP_OK;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bestP = default_split(h->Q, mode);
+  const int saved = h->split;
+  for (int P : {1, 2, 4}) {
+    if (!sweep_variant_available(h->lattice, mode, P)) continue;
+    h->split = P;
+    if (lkp_status st = enqueue_sweep(h, h->stream, h->cur, 1 - h->cur, 0, nullptr, nullptr)) {
+      h->split = saved;
+      return st;
+    }
+    HIP_TRY(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < 3; ++r)
+      if (lkp_status st = enqueue_sweep(h, h->stream, h->cur, 1 - h->cur, 0, nullptr, nullptr))
+        return st;
+    HIP_TRY(hipEventRecord(e1, h->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bestP = P;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->split = bestP;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = bestP;
+  return LKP_OK;
+}
+
+lkp_status upload_coefficients(lkp_handle *h) {
+  const int Q = h->Q;
+  std::vector<double> c64(2 * Q);
+  std::vector<float> c32(2 * Q);
+  for (int i = 0; i < Q; ++i) {
+    c64[i] = h->omega * h->phi[i];
+    c64[Q + i] = h->chi[i];
+    c32[i] = (float)c64[i];
+    c32[Q + i] = (float)h->chi[i];
+  }
+  if (h->precision == LKP_F32) {
+    HIP_TRY(hipMalloc(&h->coef, 2 * Q * sizeof(float)));
+    HIP_TRY(hipMemcpy(h->coef, c32.data(), 2 * Q * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    HIP_TRY(hipMalloc(&h->coef, 2 * Q * sizeof(double)));
+    HIP_TRY(hipMemcpy(h->coef, c64.data(), 2 * Q * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (h->precision == LKP_F32_IR) {
+    HIP_TRY(hipMalloc(&h->coef32, 2 * Q * sizeof(float)));
+    HIP_TRY(hipMemcpy(h->coef32, c32.data(), 2 * Q * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&h->phi_dev, Q * sizeof(double)));
+    HIP_TRY(hipMemcpy(h->phi_dev, h->phi.data(), Q * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return LKP_OK;
+}
+
+void release(lkp_handle *h) {
+  drop_graphs(h);
+  void *ptrs[] = {h->f[0], h->f[1], h->S, h->coef, h->coef32, h->phi_dev, h->r32, h->d32[0],
+                  h->d32[1], h->phib[0], h->phib[1], h->partials, h->norms_dev};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->norms_host) (void)hipHostFree(h->norms_host);
+  if (h->capture) (void)hipStreamDestroy(h->capture);
+}
+
+lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
+  LatticeConstants lc;
+  double tau;
+  if (lkp_status st = validate(d, &lc, &tau)) return st;
+  h->lattice = d->lattice;
+  h->order = d->order;
+  h->dim = d->dim;
+  h->precision = d->precision;
+  h->Q = lc.table.q;
+  for (int a = 0; a < 3; ++a) h->n[a] = d->n[a];
+  h->ncells = (unsigned)(d->n[0] * d->n[1] * d->n[2]);
+  h->tau_lb = tau;
+  h->omega = 1.0 / tau;
+  h->cs2 = (double)lc.cs2;
+  h->stream = (hipStream_t)d->stream;
+  std::vector<long double> phi, chi;
+  if (!shape_coefficients(lc, d->order, &phi, &chi))
+    return fail(LKP_ERR_LATTICE_ORDER, "no coefficients for order %d", d->order);
+  h->w.resize(h->Q);
+  h->phi.resize(h->Q);
+  h->chi.resize(h->Q);
+  for (int i = 0; i < h->Q; ++i) {
+    h->w[i] = (double)lc.w[i];
+    h->phi[i] = (double)phi[i];
+    h->chi[i] = (double)chi[i];
+  }
+  h->simple_wrap = h->n[0] >= max_component(lc.table, 0) && h->n[1] >= max_component(lc.table, 1) &&
+                   h->n[2] >= max_component(lc.table, 2);
+
+  // source: host copy, mean check, scaling S = s c_s^2 (tau_lb - 1/2)
+  if (!d->source) return fail(LKP_ERR_ARG, "null source");
+  const size_t n = h->ncells;
+  std::vector<double> s(n);
+  if (d->source_on_device)
+    HIP_TRY(hipMemcpy(s.data(), d->source, n * sizeof(double), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(s.data(), d->source, n * sizeof(double));
+  long double sum = 0, amax = 0;
+  for (double v : s) {
+    if (!std::isfinite(v)) return fail(LKP_ERR_ARG, "source has non-finite values");
+    sum += v;
+    amax = std::max(amax, (long double)std::fabs(v));
+  }
+  const double mean = (double)(sum / (long double)n);
+  if (std::fabs(mean) > 1e-12 * (double)amax && n > 1) {
+    if (!d->subtract_mean)
+      return fail(LKP_ERR_SOURCE_MEAN,
+                  "source mean %g is not zero: a periodic Poisson problem needs a zero-mean "
+                  "source (set subtract_mean to remove it)", mean);
+  }
+  const bool remove = d->subtract_mean != 0;
+  const double scale = h->cs2 * (h->tau_lb - 0.5);
+  std::vector<double> S(n);
+  for (size_t c = 0; c < n; ++c) S[c] = (remove ? s[c] - mean : s[c]) * scale;
+
+  // device memory
+  const size_t Q = h->Q;
+  h->footprint = footprint_of(h->precision, h->Q, h->ncells);
+  if (h->precision == LKP_F64) {
+    HIP_TRY(hipMalloc(&h->f[0], Q * n * 8));
+    HIP_TRY(hipMalloc(&h->f[1], Q * n * 8));
+    HIP_TRY(hipMalloc(&h->S, n * 8));
+    HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
+  } else if (h->precision == LKP_F32) {
+    HIP_TRY(hipMalloc(&h->f[0], Q * n * 4));
+    HIP_TRY(hipMalloc(&h->f[1], Q * n * 4));
+    std::vector<float> S32(n);
+    for (size_t c = 0; c < n; ++c) S32[c] = (float)S[c];
+    HIP_TRY(hipMalloc(&h->S, n * 4));
+    HIP_TRY(hipMemcpy(h->S, S32.data(), n * 4, hipMemcpyHostToDevice));
+  } else {
+    HIP_TRY(hipMalloc(&h->f[0], Q * n * 8));  // x, the FP64 refined state
+    h->f[1] = nullptr;
+    HIP_TRY(hipMalloc(&h->r32, Q * n * 4));
+    HIP_TRY(hipMalloc(&h->d32[0], Q * n * 4));
+    HIP_TRY(hipMalloc(&h->d32[1], Q * n * 4));
+    HIP_TRY(hipMalloc(&h->S, n * 8));
+    HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMalloc(&h->phib[0], n * 8));
+  HIP_TRY(hipMalloc(&h->phib[1], n * 8));
+  HIP_TRY(hipMalloc(&h->norms_dev, NUM_NORMS * sizeof(double)));
+  HIP_TRY(hipHostMalloc(&h->norms_host, NUM_NORMS * sizeof(double), hipHostMallocDefault));
+  // partial norms for the finest block split (P = 4: 64 cells per block)
+  if (lkp_status st = ensure_partials(h, sweep_blocks(h, 4) + 8)) return st;
+  if (lkp_status st = upload_coefficients(h)) return st;
+
+  // initial state f* = 0 (fill kernels, not memset), Phi buffers = 0
+  if (h->precision == LKP_F32) {
+    HIP_TRY(launch_fill_f32((float *)h->f[0], 0.0f, Q * n, h->stream));
+  } else {
+    HIP_TRY(launch_fill_f64((double *)h->f[0], 0.0, Q * n, h->stream));
+  }
+  HIP_TRY(launch_fill_f64(h->phib[0], 0.0, n, h->stream));
+  HIP_TRY(launch_fill_f64(h->phib[1], 0.0, n, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->split = default_split(h->Q, h->precision == LKP_F32_IR ? MODE_INNER : h->mode());
+  return LKP_OK;
+}
+
+// ---------------------------------------------------------------- F32 + IR
+
+// One sweep of the IR machinery.
+lkp_status ir_sweep(lkp_handle *h, int mode, const void *in, void *out, const void *src,
+                    int flags, const double *phi_prev, double *phi_out, int P) {
+  SweepParams p = base_params(h);
+  p.fin = in;
+  p.fout = out;
+  p.src = src;
+  p.coef = mode == MODE_INNER ? h->coef32 : h->coef;
+  p.phi_prev = phi_prev;
+  p.phi_out = phi_out;
+  p.partials = h->partials;
+  hipError_t e = launch_sweep(h->lattice, mode, P, flags, p, h->stream);
+  if (e != hipSuccess) return fail(LKP_ERR_HIP, "IR sweep launch: %s", hipGetErrorString(e));
+  return LKP_OK;
+}
+
+// r = T x + g - x in FP64 arithmetic; Phi(x) into phib[1].  Returns norms.
+lkp_status ir_residual(lkp_handle *h, double norms[NUM_NORMS]) {
+  const int P = default_split(h->Q, MODE_RESID);
+  if (lkp_status st = ir_sweep(h, MODE_RESID, h->f[0], h->r32, h->S, FLAG_REDUCE, nullptr,
+                               h->phib[1], P))
+    return st;
+  h->phi_last = 1;
+  h->phi_sweep[1] = h->total_sweeps;  // Phi of the refined state
+  return read_norms(h, sweep_blocks(h, P), norms);
+}
+
+lkp_status solve_ir(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *rep, int64_t *done) {
+  const int K = std::max(2, o->check_every);
+  const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
+  const double inner_tol = o->ir_inner_tol > 0 ? o->ir_inner_tol : 1e-4;
+  const size_t QN = (size_t)h->Q * h->ncells;
+  double nr[NUM_NORMS];
+  h->total_sweeps += 1;  // each FP64 residual evaluation is one sweep of x
+  *done += 1;
+  if (lkp_status st = ir_residual(h, nr)) return st;
+  double rnorm = std::sqrt(nr[NORM_SUM_R2]);
+  double corr_prev = -1, rnorm_prev = -1;
+  int outer = 0;
+  double rate = 0;
+  for (;;) {
+    const double phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
+    rep->phi_l2 = phi_l2;
+    rep->mass = nr[NORM_SUM_PHI];
+    if (nr[NORM_BAD] > 0) return fail(LKP_ERR_DIVERGED, "non-finite residual");
+    if (corr_prev >= 0 && rnorm_prev > 0 && phi_l2 > 0) {
+      rep->est_rel_err = corr_prev * (rnorm / rnorm_prev) / phi_l2;
+      if (rep->est_rel_err <= o->tol_rel_l2) return LKP_OK;
+    }
+    if (rnorm == 0) {
+      rep->est_rel_err = 0;
+      return LKP_OK;
+    }
+    if (outer >= max_outer) return fail(LKP_ERR_NOT_CONVERGED, "refinement: %d outer steps", outer);
+    if (*done >= o->max_sweeps) return fail(LKP_ERR_NOT_CONVERGED, "refinement: max_sweeps");
+    // inner: d <- T d + r from d = 0, FP32
+    HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
+    int dc = 0;
+    double l2_prev = -1, corr = 0, best_l2 = 1e300;
+    int stall = 0;
+    int64_t t_prev = 0, t_in = 0;
+    const int P = h->split;
+    for (;;) {
+      for (int j = 0; j < K; ++j) {
+        int flags = 0;
+        double *po = nullptr;
+        const double *pp = nullptr;
+        if (j == K - 2) { flags = FLAG_PHI; po = h->phib[0]; }
+        if (j == K - 1) { flags = FLAG_REDUCE; pp = h->phib[0]; po = h->phib[1]; }
+        if (lkp_status st = ir_sweep(h, MODE_INNER, h->d32[dc], h->d32[1 - dc], h->r32, flags, pp,
+                                     po, P))
+          return st;
+        dc = 1 - dc;
+      }
+      t_in += K;
+      *done += K;
+      h->total_sweeps += K;
+      double ni[NUM_NORMS];
+      if (lkp_status st = read_norms(h, sweep_blocks(h, P), ni)) return st;
+      if (ni[NORM_BAD] > 0) return fail(LKP_ERR_DIVERGED, "non-finite inner sweep");
+      const double l2 = std::sqrt(ni[NORM_SUM_DPHI2]);
+      corr = std::sqrt(ni[NORM_SUM_PHI2]);
+      if (l2_prev > 0 && l2 > 0) {
+        const double r = std::pow(l2 / l2_prev, 1.0 / (double)(t_in - t_prev));
+        if (r < 1) rate = r;
+      }
+      stall = (l2 < 0.95 * best_l2) ? 0 : stall + 1;
+      best_l2 = std::min(best_l2, l2);
+      l2_prev = l2;
+      t_prev = t_in;
+      const double est = (rate > 0 && rate < 1) ? l2 * rate / (1 - rate) : 1e300;
+      if (corr == 0 || est <= inner_tol * corr || stall >= 3 || *done >= o->max_sweeps) break;
+    }
+    rep->rate = rate;
+    // x += d - phi_i * mean(d): FP64 accumulation with the mass mode removed
+    unsigned nb = 0;
+    HIP_TRY(launch_sum_f32(h->d32[dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream));
+    HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
+    HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[dc], h->phi_dev, h->norms_dev, h->Q,
+                             h->ncells, h->stream));
+    ++outer;
+    rep->outer = outer;
+    corr_prev = corr;
+    rnorm_prev = rnorm;
+    h->total_sweeps += 1;
+    *done += 1;
+    if (lkp_status st = ir_residual(h, nr)) return st;
+    rnorm = std::sqrt(nr[NORM_SUM_R2]);
+  }
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char *lkp_last_error(void) { return g_err.c_str(); }
+
+int64_t lkp_footprint_bytes(const lkp_problem_desc *d) {
+  LatticeConstants lc;
+  double tau;
+  std::string keep = g_err;
+  if (validate(d, &lc, &tau) != LKP_OK) {
+    g_err = keep;
+    return 0;
+  }
+  return footprint_of(d->precision, lc.table.q, d->n[0] * d->n[1] * d->n[2]);
+}
+
+lkp_status lkp_create(const lkp_problem_desc *d, lkp_handle **out) {
+  if (!out) return fail(LKP_ERR_ARG, "null output handle pointer");
+  *out = nullptr;
+  lkp_handle *h = new lkp_handle();
+  lkp_status st = create_impl(d, h);
+  if (st != LKP_OK) {
+    release(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  g_err.clear();
+  return LKP_OK;
+}
+
+lkp_status lkp_destroy(lkp_handle *h) {
+  if (!h) return LKP_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  release(h);
+  delete h;
+  return LKP_OK;
+}
+
+lkp_status lkp_step(lkp_handle *h, int64_t sweeps) {
+  if (!h || sweeps < 0) return fail(LKP_ERR_ARG, "lkp_step: bad arguments");
+  if (sweeps == 0) return LKP_OK;
+  if (h->precision == LKP_F32_IR)
+    return fail(LKP_ERR_UNSUPPORTED, "lkp_step drives the plain sweep; F32_IR handles use lkp_solve");
+  if (lkp_status st = tune_split(h)) return st;
+  int cur = h->cur;
+  for (int64_t j = 0; j < sweeps - 1; ++j) {
+    if (lkp_status st = enqueue_sweep(h, h->stream, cur, 1 - cur, 0, nullptr, nullptr)) return st;
+    cur = 1 - cur;
+  }
+  const int b = 1 - h->phi_last;
+  if (lkp_status st = enqueue_sweep(h, h->stream, cur, 1 - cur, FLAG_PHI, nullptr, h->phib[b]))
+    return st;
+  cur = 1 - cur;
+  h->cur = cur;
+  h->total_sweeps += sweeps;
+  h->phi_last = b;
+  h->phi_sweep[b] = h->total_sweeps;
+  HIP_TRY(hipGetLastError());
+  return LKP_OK;
+}
+
+lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *rep_out) {
+  if (!h || !o) return fail(LKP_ERR_ARG, "lkp_solve: null argument");
+  if (o->check_every < 1 || o->max_sweeps < 1)
+    return fail(LKP_ERR_ARG, "lkp_solve: check_every and max_sweeps must be >= 1");
+  if (!(o->tol_rel_l2 > 0) && !(o->tol_maxchange > 0))
+    return fail(LKP_ERR_ARG, "lkp_solve: give tol_rel_l2 or tol_maxchange");
+  lkp_solve_report rep{};
+  const double t_start = now_s();
+  int64_t done = 0;
+  lkp_status result = LKP_OK;
+  if (lkp_status st = tune_split(h)) return st;
+
+  if (h->precision == LKP_F32_IR) {
+    if (!(o->tol_rel_l2 > 0)) return fail(LKP_ERR_ARG, "F32_IR needs tol_rel_l2");
+    result = solve_ir(h, o, &rep, &done);
+  } else {
+    double l2_prev = -1, min_l2 = 1e300;
+    int64_t t_prev = -1;
+    bool converged = false;
+    while (!converged) {
+      if (done >= o->max_sweeps) {
+        result = fail(LKP_ERR_NOT_CONVERGED, "no convergence in %lld sweeps",
+                      (long long)o->max_sweeps);
+        break;
+      }
+      const int k = (int)std::min<int64_t>(o->check_every, o->max_sweeps - done);
+      // a one-sweep chunk compares with the previous sweep's Phi only if it exists
+      const int a = h->phi_last;
+      const bool prev_ok =
+          k >= 2 ? (h->total_sweeps + k >= 2) : (h->phi_sweep[a] == h->total_sweeps && h->total_sweeps >= 1);
+      if (lkp_status st = run_chunk(h, k, o->use_graph != 0)) return st;
+      done += k;
+      double nr[NUM_NORMS];
+      if (lkp_status st = read_norms(h, sweep_blocks(h, h->split), nr)) return st;
+      if (nr[NORM_BAD] > 0) {
+        result = fail(LKP_ERR_DIVERGED, "non-finite values after %lld sweeps",
+                      (long long)h->total_sweeps);
+        break;
+      }
+      rep.max_change = nr[NORM_MAX_DPHI];
+      rep.l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
+      rep.phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
+      rep.mass = nr[NORM_SUM_PHI];
+      if (!prev_ok) continue;
+      const double l2 = rep.l2_change;
+      if (l2_prev > 0 && l2 > 0 && h->total_sweeps > t_prev) {
+        const double r = std::pow(l2 / l2_prev, 1.0 / (double)(h->total_sweeps - t_prev));
+        rep.rate = r;
+      }
+      if (l2 > 0) min_l2 = std::min(min_l2, l2);
+      if (l2 > 1e10 * min_l2 && l2 > 1e-300) {
+        result = fail(LKP_ERR_DIVERGED, "change grew by 1e10 (unstable tau_lb?)");
+        break;
+      }
+      if (o->tol_maxchange > 0 && rep.max_change < o->tol_maxchange) converged = true;
+      if (o->tol_rel_l2 > 0) {
+        if (l2 == 0) {
+          rep.est_rel_err = 0;
+          converged = true;
+        } else if (rep.rate > 0 && rep.rate < 1 && rep.phi_l2 > 0) {
+          rep.est_rel_err = l2 * rep.rate / (1 - rep.rate) / rep.phi_l2;
+          if (rep.est_rel_err <= o->tol_rel_l2) converged = true;
+        } else {
+          rep.est_rel_err = INFINITY;
+        }
+      }
+      l2_prev = l2;
+      t_prev = h->total_sweeps;
+    }
+  }
+  rep.wall_s = now_s() - t_start;
+  rep.sweeps = done;
+  rep.total_sweeps = h->total_sweeps;
+  rep.glups = rep.wall_s > 0 ? 1e-9 * (double)h->ncells * (double)done / rep.wall_s : 0;
+  rep.status = result;
+  if (rep_out) *rep_out = rep;
+  if (result == LKP_OK) g_err.clear();
+  return result;
+}
+
+lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r) {
+  if (!h || !r) return fail(LKP_ERR_ARG, "lkp_residual: null argument");
+  std::memset(r, 0, sizeof *r);
+  r->sweeps = h->total_sweeps;
+  if (h->precision == LKP_F32_IR) {
+    double nr[NUM_NORMS];
+    const int last = h->phi_last;
+    const int P = default_split(h->Q, MODE_RESID);
+    if (lkp_status st = ir_sweep(h, MODE_RESID, h->f[0], h->r32, h->S, FLAG_REDUCE,
+                                 h->phib[last], h->phib[1 - last], P))
+      return st;
+    if (lkp_status st = read_norms(h, sweep_blocks(h, P), nr)) return st;
+    r->max_change = nr[NORM_MAX_DPHI];
+    r->l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
+    r->pop_residual_l2 = std::sqrt(nr[NORM_SUM_R2]);
+    r->phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
+    r->mass = nr[NORM_SUM_PHI];
+    h->phi_sweep[1 - last] = -1;
+    return LKP_OK;
+  }
+  const int last = h->phi_last;
+  if (h->total_sweeps < 1 || h->phi_sweep[last] != h->total_sweeps)
+    return fail(LKP_ERR_STATE, "lkp_residual needs the Phi of the last sweep (run a sweep first)");
+  const int scratch = 1 - last;
+  double nr[NUM_NORMS];
+  if (h->precision == LKP_F64) {
+    // FP64 residual: one sweep into the idle buffer (used as FP32 r storage)
+    const int P = default_split(h->Q, MODE_RESID);
+    if (lkp_status st = ir_sweep(h, MODE_RESID, h->f[h->cur], h->f[1 - h->cur], h->S, FLAG_REDUCE,
+                                 h->phib[last], h->phib[scratch], P))
+      return st;
+    if (lkp_status st = read_norms(h, sweep_blocks(h, P), nr)) return st;
+    r->pop_residual_l2 = std::sqrt(nr[NORM_SUM_R2]);
+  } else {
+    if (lkp_status st = enqueue_sweep(h, h->stream, h->cur, 1 - h->cur, FLAG_REDUCE, h->phib[last],
+                                      h->phib[scratch]))
+      return st;
+    if (lkp_status st = read_norms(h, sweep_blocks(h, h->split), nr)) return st;
+    r->pop_residual_l2 = NAN;
+  }
+  h->phi_sweep[scratch] = -1;
+  r->max_change = nr[NORM_MAX_DPHI];
+  r->l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
+  r->phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
+  r->mass = nr[NORM_SUM_PHI];
+  return LKP_OK;
+}
+
+lkp_status lkp_get_phi(lkp_handle *h, double *dst, int32_t dst_is_device) {
+  if (!h || !dst) return fail(LKP_ERR_ARG, "lkp_get_phi: null argument");
+  const int last = h->phi_last;
+  if (h->phi_sweep[last] != h->total_sweeps || h->total_sweeps < 1)
+    return fail(LKP_ERR_STATE, "no Phi for the current state (run a sweep first)");
+  HIP_TRY(hipMemcpyAsync(dst, h->phib[last], (size_t)h->ncells * 8,
+                         dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LKP_OK;
+}
+
+lkp_status lkp_get_populations(lkp_handle *h, double *dst, int32_t dst_is_device) {
+  if (!h || !dst) return fail(LKP_ERR_ARG, "lkp_get_populations: null argument");
+  const size_t QN = (size_t)h->Q * h->ncells;
+  if (h->precision == LKP_F32) {
+    double *tmp = dst;
+    if (!dst_is_device) HIP_TRY(hipMalloc(&tmp, QN * 8));
+    HIP_TRY(launch_f32_to_f64((const float *)h->f[h->cur], tmp, QN, h->stream));
+    if (!dst_is_device) {
+      HIP_TRY(hipMemcpyAsync(dst, tmp, QN * 8, hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      HIP_TRY(hipFree(tmp));
+    }
+  } else {
+    const void *srcp = h->precision == LKP_F64 ? h->f[h->cur] : h->f[0];
+    HIP_TRY(hipMemcpyAsync(dst, srcp, QN * 8,
+                           dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           h->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LKP_OK;
+}
+
+lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_device) {
+  if (!h || !src) return fail(LKP_ERR_ARG, "lkp_set_populations: null argument");
+  const size_t QN = (size_t)h->Q * h->ncells;
+  const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (h->precision == LKP_F32) {
+    double *tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, QN * 8));
+    HIP_TRY(hipMemcpyAsync(tmp, src, QN * 8, kind, h->stream));
+    HIP_TRY(launch_f64_to_f32(tmp, (float *)h->f[h->cur], QN, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipFree(tmp));
+  } else {
+    void *dstp = h->precision == LKP_F64 ? h->f[h->cur] : h->f[0];
+    HIP_TRY(hipMemcpyAsync(dstp, src, QN * 8, kind, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  h->phi_sweep[0] = h->phi_sweep[1] = -1;
+  return LKP_OK;
+}
+
+lkp_status lkp_lattice_info(int32_t lattice, int32_t order, int32_t *Q, int32_t *dim, int32_t *v,
+                            double *w, double *phi, double *chi, double *cs2) {
+  if (lattice < 0 || lattice >= LKP_NUM_LATTICES) return fail(LKP_ERR_ARG, "unknown lattice");
+  LatticeConstants lc;
+  if (!lattice_constants(lattice, &lc)) return fail(LKP_ERR_HIP, "lattice constant solve failed");
+  std::vector<long double> ph, ch;
+  if ((phi || chi) && !shape_coefficients(lc, order, &ph, &ch))
+    return fail(LKP_ERR_LATTICE_ORDER, "order %d not available on this lattice", order);
+  const int q = lc.table.q;
+  if (Q) *Q = q;
+  if (dim) *dim = lc.table.dim;
+  if (cs2) *cs2 = (double)lc.cs2;
+  for (int i = 0; i < q; ++i) {
+    if (v)
+      for (int a = 0; a < 3; ++a) v[3 * i + a] = lc.table.v[i][a];
+    if (w) w[i] = (double)lc.w[i];
+    if (phi) phi[i] = (double)ph[i];
+    if (chi) chi[i] = (double)ch[i];
+  }
+  return LKP_OK;
+}
+
+lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info) {
+  if (!h || !info) return fail(LKP_ERR_ARG, "lkp_get_info: null argument");
+  info->lattice = h->lattice;
+  info->order = h->order;
+  info->dim = h->dim;
+  info->Q = h->Q;
+  info->precision = h->precision;
+  info->velocity_groups = h->split;
+  for (int a = 0; a < 3; ++a) info->n[a] = h->n[a];
+  info->tau_lb = h->tau_lb;
+  info->omega = h->omega;
+  info->cs2 = h->cs2;
+  info->total_sweeps = h->total_sweeps;
+  info->footprint_bytes = h->footprint;
+  return LKP_OK;
+}
+
+lkp_status lkp_sync(lkp_handle *h) {
+  if (!h) return fail(LKP_ERR_ARG, "lkp_sync: null handle");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LKP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,6 @@
+// Fused sweep kernels for D1Q9 (all precision modes and velocity splits).
+#include "sweep_impl.hpp"
+
+namespace lkp {
+template hipError_t launch_lattice_tu<D1Q9>(int, int, int, SweepParams, hipStream_t);
+}  // namespace lkp

@@ -1,0 +1,6 @@
+// Fused sweep kernels for D2Q81 (all precision modes and velocity splits).
+#include "sweep_impl.hpp"
+
+namespace lkp {
+template hipError_t launch_lattice_tu<D2Q81>(int, int, int, SweepParams, hipStream_t);
+}  // namespace lkp

@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI (no GPU needed): exports, constants, validation."""
+import ctypes
+import os
+import re
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import paper_1504_05869_amd as lkp
+from paper_1504_05869_amd import _lib
+from oracle import lattice as OL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lkp.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    decl = re.compile(r"^(?:const\s+)?\w+\s*\*?\s*(lkp_[a-z_]+)\s*\(", re.M)
+    return sorted(set(decl.findall(txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(_lib.EXPORTS) <= set(names)
+
+
+@pytest.mark.parametrize("name", list(_lib.LATTICES))
+def test_product_constants_match_oracle(name):
+    """The library's long-double weights, c_s^2, phi_i and chi_i agree with
+    the oracle's 50-digit values (two independent derivations)."""
+    ol = OL.get(name)
+    for order in (1, 3, 5, 7):
+        if order > ol.max_order:
+            continue
+        info = lkp.lattice_info(name, order)
+        assert info["Q"] == ol.Q and info["dim"] == ol.dim
+        assert abs(info["cs2"] - ol.c2) <= 2e-16 * ol.c2
+        # map velocities
+        idx = {tuple(int(c) for c in v): i for i, v in enumerate(ol.v3())}
+        perm = [idx[tuple(int(c) for c in v)] for v in info["v"]]
+        assert sorted(perm) == list(range(ol.Q))
+        phi, chi = OL.coefficients(ol, order)
+        w = ol.w
+        assert np.allclose(info["w"], w[perm], rtol=4e-16, atol=1e-22)
+        scale = np.abs(phi).max()
+        assert np.abs(info["phi"] - phi[perm]).max() <= 4e-16 * scale
+        assert np.abs(info["chi"] - chi[perm]).max() <= 4e-16 * np.abs(chi).max()
+
+
+def test_d3q111_velocity_table():
+    info = lkp.lattice_info("D3Q111", 5)
+    v = info["v"]
+    assert len({tuple(x) for x in v.tolist()}) == 111
+    assert (np.abs(v) <= 3).all()
+    assert abs(info["w"].sum() - 1) < 1e-15
+
+
+def _desc(**kw):
+    args = dict(shape=(16, 16), lattice="D2Q25", order=3, tau_lb=1.0, knudsen=None,
+                precision="f64", subtract_mean=False, allow_unstable=False)
+    args.update(kw)
+    return lkp._desc(args["shape"], args["lattice"], args["order"], args["tau_lb"],
+                     args["knudsen"], args["precision"], args["subtract_mean"],
+                     args["allow_unstable"])
+
+
+def _create_status(source, **kw):
+    d = _desc(shape=source.shape, **kw)
+    src = np.ascontiguousarray(source, dtype=np.float64)
+    d.source = src.ctypes.data
+    d.source_on_device = 0
+    h = ctypes.c_void_p()
+    st = _lib.load().lkp_create(ctypes.byref(d), ctypes.byref(h))
+    msg = _lib.load().lkp_last_error().decode()
+    if h.value:
+        _lib.load().lkp_destroy(h)
+    return _lib.STATUS[st], msg
+
+
+def test_create_rejects_bad_order_and_dim():
+    s = np.zeros((16, 16))
+    assert _create_status(s, order=5)[0] == "LKP_ERR_LATTICE_ORDER"     # D2Q25 is N <= 3
+    assert _create_status(s, order=4)[0] == "LKP_ERR_LATTICE_ORDER"
+    assert _create_status(s, lattice="D3Q111", order=5)[0] == "LKP_ERR_LATTICE_ORDER"
+    assert _create_status(s, lattice="D2Q5", order=3)[0] == "LKP_ERR_LATTICE_ORDER"
+
+
+def test_create_rejects_unstable_tau():
+    s = np.zeros((16, 16))
+    st, msg = _create_status(s, lattice="D2Q169", order=7, tau_lb=0.7)
+    assert st == "LKP_ERR_UNSTABLE" and "stability" in msg
+    assert _create_status(s, tau_lb=0.5)[0] == "LKP_ERR_UNSTABLE"
+
+
+def test_create_rejects_nonzero_mean_source():
+    s = np.ones((16, 16))
+    st, msg = _create_status(s)
+    assert st == "LKP_ERR_SOURCE_MEAN" and "mean" in msg
+
+
+def test_footprint_matches_formula():
+    # F64: 2 population buffers of 8 Q n bytes dominate
+    n = 1024 * 1024
+    fb = lkp.footprint_bytes((1024, 1024), "D2Q81", 5, knudsen=0.1)
+    assert 2 * 8 * 81 * n < fb < 2 * 8 * 81 * n * 1.05
+    fb32 = lkp.footprint_bytes((1024, 1024), "D2Q81", 5, knudsen=0.1, precision="f32")
+    assert 2 * 4 * 81 * n < fb32 < 2 * 4 * 81 * n * 1.1
+    assert lkp.footprint_bytes((16, 16), "D2Q25", 5, tau_lb=1.0) == 0
+
+
+def test_knudsen_mapping_matches_oracle():
+    d = _desc(shape=(1024, 1024), lattice="D2Q81", order=5, tau_lb=None, knudsen=0.1)
+    # validation runs on the host; recompute tau from the oracle's constants
+    tau = OL.tau_from_knudsen(0.1, OL.get("D2Q81"), 1024)
+    assert 118.0 < tau < 118.6
+    assert d.knudsen == 0.1

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle (needs gfx950)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1504_05869_amd as lkp
+from paper_1504_05869_amd import workloads as W
+from oracle import lattice as OL
+from oracle import spectral as SP
+from oracle import sweep as SW
+
+pytestmark = pytest.mark.gpu
+
+ORDER = {"D1Q5": 3, "D1Q9": 5, "D1Q13": 7, "D2Q5": 1, "D2Q9": 3, "D2Q25": 3, "D2Q81": 5,
+         "D2Q169": 7, "D3Q111": 5}
+# ragged shapes spanning several 256-cell blocks (numpy order: (nz,) ny, nx)
+SHAPES = {"D1Q5": (333,), "D1Q9": (301,), "D1Q13": (257,), "D2Q5": (23, 37), "D2Q9": (23, 37),
+          "D2Q25": (29, 41), "D2Q81": (31, 45), "D2Q169": (27, 33), "D3Q111": (9, 11, 13)}
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def perm(lattice):
+    """perm[i] = oracle index of the product's velocity i."""
+    info = lkp.lattice_info(lattice, 1)
+    ol = OL.get(lattice)
+    idx = {tuple(int(c) for c in v): i for i, v in enumerate(ol.v3())}
+    return np.array([idx[tuple(int(c) for c in v)] for v in info["v"]])
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def k_sweep_case(lattice, shape, tau, sweeps, precision="f64", seed=1, split=None):
+    say("k-sweep", lattice, shape, "tau", tau, "sweeps", sweeps, precision, "split", split)
+    order = ORDER[lattice]
+    rng = np.random.default_rng(seed)
+    s = W.zero_mean(rng.standard_normal(shape))
+    f0 = rng.standard_normal((OL.get(lattice).Q,) + tuple(shape))
+    pm = perm(lattice)
+    if split is not None:
+        os.environ["LKP_SPLIT"] = str(split)
+    try:
+        with lkp.Problem(s, lattice, order, tau_lb=tau, precision=precision) as p:
+            p.set_populations(f0[pm])
+            p.step(sweeps)
+            phi_gpu = p.phi_host()
+            pop_gpu = p.populations()
+            groups = p.info()["velocity_groups"]
+    finally:
+        os.environ.pop("LKP_SPLIT", None)
+    prob = SW.Problem(lattice, order, tau, s)
+    phi_ref, pop_ref = SW.run(prob, sweeps, f0)
+    return rel_l2(phi_gpu, phi_ref), rel_l2(pop_gpu, pop_ref[pm]), groups
+
+
+@pytest.mark.parametrize("lattice", list(SHAPES))
+def test_k_sweep_parity_f64(lattice):
+    e_phi, e_pop, _ = k_sweep_case(lattice, SHAPES[lattice], 1.3, 5)
+    say(lattice, "rel-L2 phi", e_phi, "pops", e_pop)
+    assert e_phi <= 1e-13 and e_pop <= 1e-13
+
+
+@pytest.mark.parametrize("lattice,split", [("D2Q81", 1), ("D2Q81", 2), ("D2Q169", 2),
+                                           ("D2Q169", 4), ("D3Q111", 2), ("D3Q111", 4)])
+def test_k_sweep_parity_every_split_f64(lattice, split):
+    e_phi, e_pop, groups = k_sweep_case(lattice, SHAPES[lattice], 2.0, 4, split=split)
+    assert groups == split
+    assert e_phi <= 1e-13 and e_pop <= 1e-13
+
+
+@pytest.mark.parametrize("lattice,shape", [("D2Q169", (4, 5)), ("D3Q111", (2, 3, 2)),
+                                           ("D1Q13", (4,)), ("D2Q81", (1, 7)), ("D2Q25", (1, 1))])
+def test_grids_smaller_than_velocities(lattice, shape):
+    """Axes shorter than the largest velocity wrap several times."""
+    e_phi, e_pop, _ = k_sweep_case(lattice, shape, 1.5, 3)
+    assert e_phi <= 1e-13 and e_pop <= 1e-13
+
+
+@pytest.mark.parametrize("lattice,split", [("D2Q81", 1), ("D2Q169", 1), ("D2Q169", 2),
+                                           ("D3Q111", 1), ("D3Q111", 2), ("D2Q25", 1)])
+def test_k_sweep_parity_f32(lattice, split):
+    e_phi, e_pop, _ = k_sweep_case(lattice, SHAPES[lattice], 1.3, 5, precision="f32",
+                                   split=split)
+    say(lattice, "f32 rel-L2 phi", e_phi, "pops", e_pop)
+    assert e_phi <= 2e-6 and e_pop <= 2e-6
+
+
+def _blobs(shape, seed=3):
+    return W.zero_mean(W.gaussian_blobs(shape, 6, 1.5, seed))
+
+
+@pytest.mark.parametrize("lattice,shape,tau", [("D2Q81", (40, 48), 2.0), ("D2Q169", (36, 30), 1.0),
+                                               ("D2Q25", (50, 44), 5.0), ("D3Q111", (10, 12, 16), 1.0),
+                                               ("D1Q13", (96,), 1.0)])
+def test_converged_f64_matches_spectral(lattice, shape, tau):
+    say("converged f64", lattice, shape, tau)
+    s = _blobs(shape)
+    with lkp.Problem(s, lattice, ORDER[lattice], tau_lb=tau) as p:
+        rep = p.solve(tol_rel_l2=1e-12, check_every=50, max_sweeps=500000)
+        phi = p.phi_host()
+    ref = SP.fixed_point(lattice, ORDER[lattice], tau, s)
+    err = rel_l2(phi, ref)
+    say(lattice, "sweeps", rep["sweeps"], "est", rep["est_rel_err"], "true", err)
+    assert err <= 1e-10
+    assert rep["est_rel_err"] <= 1e-12
+
+
+def test_config1_stop_rule_matches_oracle():
+    """64x64 D2Q5, tau_lb = 1, max|dPhi| < 1e-10 checked every sweep."""
+    s = W.sine_product((64, 64))
+    with lkp.Problem(s, "D2Q5", 1, tau_lb=1.0) as p:
+        rep = p.solve(tol_maxchange=1e-10, check_every=1, max_sweeps=100000)
+        phi = p.phi_host()
+    phi_ref, sweeps_ref, _ = SW.solve_maxchange(SW.Problem("D2Q5", 1, 1.0, s), 1e-10, 100000)
+    say("config1 sweeps gpu", rep["sweeps"], "oracle", sweeps_ref, "rel-L2", rel_l2(phi, phi_ref))
+    # same velocity order and per-operation rounding: the stop decision, taken
+    # 5e-15 below the threshold, must come out the same
+    assert rep["sweeps"] == sweeps_ref
+    assert rel_l2(phi, phi_ref) <= 1e-15
+    assert abs(phi[16, 16] - 51.7514661) < 1e-6
+
+
+@pytest.mark.parametrize("lattice,shape,tau", [("D2Q81", (48, 64), 4.0), ("D3Q111", (12, 10, 16), 1.0),
+                                               ("D2Q169", (40, 36), 9.0)])
+def test_f32_ir_reaches_fp64_accuracy(lattice, shape, tau):
+    say("f32-ir", lattice, shape, tau)
+    s = _blobs(shape, seed=5)
+    ref = SP.fixed_point(lattice, ORDER[lattice], tau, s)
+    for tol, bar in [(1e-7, 1e-6), (1e-11, 1e-10)]:
+        with lkp.Problem(s, lattice, ORDER[lattice], tau_lb=tau, precision="f32_ir") as p:
+            rep = p.solve(tol_rel_l2=tol, check_every=50, max_sweeps=400000)
+            phi = p.phi_host()
+        err = rel_l2(phi, ref)
+        say(lattice, "tol", tol, "outer", rep["outer"], "sweeps", rep["sweeps"], "true", err)
+        assert err <= bar
+
+
+def test_f32_plain_stagnates_above_fp64():
+    """Without refinement the FP32 sweep stalls near its rounding floor."""
+    s = _blobs((48, 64), seed=5)
+    ref = SP.fixed_point("D2Q81", 5, 4.0, s)
+    with lkp.Problem(s, "D2Q81", 5, tau_lb=4.0, precision="f32") as p:
+        p.solve(tol_rel_l2=1e-12, max_sweeps=20000, raise_on_error=False)
+        err = rel_l2(p.phi_host(), ref)
+    say("plain f32 floor", err)
+    assert 1e-9 < err < 1e-3
+
+
+def test_deterministic_graph_and_eager_agree_bitwise():
+    s = _blobs((64, 80), seed=7)
+    out = []
+    for use_graph in (True, True, False):
+        with lkp.Problem(s, "D2Q81", 5, tau_lb=3.0) as p:
+            p.solve(tol_rel_l2=1e-9, check_every=40, use_graph=use_graph)
+            out.append(p.phi_host())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_shift_equivariance_bitwise():
+    s = _blobs((40, 56), seed=9)
+    res = []
+    for src in (s, np.roll(s, (3, 5), axis=(0, 1))):
+        with lkp.Problem(src, "D2Q169", 7, tau_lb=1.0) as p:
+            p.step(60)
+            res.append(p.phi_host())
+    assert np.array_equal(np.roll(res[0], (3, 5), axis=(0, 1)), res[1])
+
+
+def test_residual_report_matches_oracle():
+    lattice, shape, tau = "D2Q81", (20, 24), 1.7
+    rng = np.random.default_rng(4)
+    s = W.zero_mean(rng.standard_normal(shape))
+    f0 = rng.standard_normal((81,) + shape)
+    pm = perm(lattice)
+    with lkp.Problem(s, lattice, 5, tau_lb=tau) as p:
+        p.set_populations(f0[pm])
+        p.step(3)
+        r = p.residual()
+        phi3 = p.phi_host()
+        r2 = p.residual()
+        assert np.array_equal(p.phi_host(), phi3)     # no state change
+    prob = SW.Problem(lattice, 5, tau, s)
+    phi_a, f3 = SW.run(prob, 3, f0)
+    phi_b, f4 = SW.run(prob, 1, f3)
+    assert abs(r["max_change"] - np.abs(phi_b - phi_a).max()) <= 1e-12 * np.abs(phi_a).max()
+    ref_res = np.linalg.norm(f4 - f3)
+    assert abs(r["pop_residual_l2"] - ref_res) <= 1e-6 * ref_res   # r stored via FP32
+    assert r == r2
+
+
+def test_checkpoint_resume_bitwise():
+    s = _blobs((30, 50), seed=2)
+    with lkp.Problem(s, "D2Q25", 3, tau_lb=2.0) as p:
+        p.step(17)
+        f = p.populations()
+        p.step(11)
+        a = p.phi_host()
+        p.set_populations(f)
+        with pytest.raises(lkp.LkpError):
+            p.phi_host()        # no Phi for a state that was set, until a sweep
+        p.step(11)
+        b = p.phi_host()
+    assert np.array_equal(a, b)
+
+
+def test_mass_stays_zero():
+    s = _blobs((32, 32), seed=11)
+    with lkp.Problem(s, "D2Q169", 7, tau_lb=5.0) as p:
+        rep = p.solve(tol_rel_l2=1e-10, check_every=25)
+    assert abs(rep["mass"]) <= 1e-10 * rep["phi_l2"] * 32
+
+
+def test_divergence_is_reported():
+    s = _blobs((32, 32), seed=1)
+    with lkp.Problem(s, "D2Q169", 7, tau_lb=0.55, allow_unstable=True) as p:
+        with pytest.raises(lkp.LkpError) as ei:
+            p.solve(tol_rel_l2=1e-10, check_every=20, max_sweeps=200000)
+    assert ei.value.name == "LKP_ERR_DIVERGED"
+
+
+def test_not_converged_is_reported_and_resumable():
+    s = _blobs((32, 32), seed=1)
+    with lkp.Problem(s, "D2Q25", 3, tau_lb=1.0) as p:
+        with pytest.raises(lkp.LkpError) as ei:
+            p.solve(tol_rel_l2=1e-12, check_every=10, max_sweeps=30)
+        assert ei.value.name == "LKP_ERR_NOT_CONVERGED"
+        rep = p.solve(tol_rel_l2=1e-8, check_every=50)
+        assert rep["total_sweeps"] == 30 + rep["sweeps"]
+
+
+def test_device_source_and_phi_tensor():
+    s = _blobs((24, 40), seed=6)
+    st = torch.from_numpy(s).cuda()
+    with lkp.Problem(st, "D2Q81", 5, tau_lb=2.0) as p:
+        p.step(10)
+        out = p.phi()
+        assert out.is_cuda and out.dtype == torch.float64
+        ref, _ = SW.run(SW.Problem("D2Q81", 5, 2.0, s), 10)
+        assert rel_l2(out.cpu().numpy(), ref) <= 1e-13
+
+
+def test_full_size_config2_d2q81_fp64():
+    """1024^2, D2Q81, N = 5, Kn = 0.1, 64 Gaussians: converged FP64 answer vs
+    the exact spectral fixed point, plus 3 sweeps from a random state vs the
+    C oracle at full size."""
+    shape = (1024, 1024)
+    s = W.poisson_source("blobs2d", shape, seed=12345)
+    ol = OL.get("D2Q81")
+    tau = OL.tau_from_knudsen(0.1, ol, 1024)
+    say("full size solve, tau", tau)
+    with lkp.Problem(s, "D2Q81", 5, knudsen=0.1) as p:
+        assert abs(p.info()["tau_lb"] - tau) < 1e-12
+        rep = p.solve(tol_rel_l2=1e-11, check_every=100, max_sweeps=200000)
+        phi = p.phi_host()
+    ref = SP.fixed_point("D2Q81", 5, tau, s)
+    err = rel_l2(phi, ref)
+    say("full size: sweeps", rep["sweeps"], "glups", rep["glups"], "true err", err)
+    assert err <= 1e-10
+    e_phi, e_pop, _ = k_sweep_case("D2Q81", shape, tau, 3)
+    say("full size k-sweep", e_phi, e_pop)
+    assert e_phi <= 1e-13 and e_pop <= 1e-13
