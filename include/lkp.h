@@ -79,7 +79,7 @@ typedef struct lkp_problem_desc {
   int32_t dim;              /* 1, 2 or 3; must equal the lattice's dimension */
   int32_t lattice;          /* lkp_lattice */
   int64_t n[3];             /* nx, ny, nz; axes beyond dim must be 1; each >= 1;
-                               nx*ny*nz < 2^31 */
+                               nx*ny*nz < 2^29 (a population plane stays below 4 GiB) */
   int32_t order;            /* expansion order N: 1, 3, 5 or 7 (Sec. 3) */
   int32_t precision;        /* lkp_precision */
   double tau_lb;            /* lattice relaxation time; used when knudsen <= 0 */
@@ -120,8 +120,8 @@ typedef struct lkp_solve_opts {
   int64_t max_sweeps;   /* hard cap on sweeps done by this call (> 0) */
   int32_t check_every;  /* sweeps between convergence checks (>= 1) */
   int32_t max_outer;    /* LKP_F32_IR: cap on refinement steps (0 = 20) */
-  double ir_inner_tol;  /* LKP_F32_IR: relative reduction of the correction per inner
-                           solve (0 = 1e-4) */
+  double ir_inner_tol;  /* LKP_F32_IR: relative accuracy of each inner solve; 0 = adaptive,
+                           0.3 tol_rel_l2 / (current estimated error), within [1e-7, 0.1] */
   int32_t use_graph;    /* 1: replay the chunk of sweeps as a captured hipGraph */
   int32_t reserved;
 } lkp_solve_opts;
@@ -197,6 +197,68 @@ lkp_status lkp_sync(lkp_handle *h);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *lkp_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Serving: many resident problems advanced together.
+ *
+ * A group holds problems of one class (lattice, order, precision) that share
+ * the group's stream.  lkp_group_step advances every running member by the
+ * same number of sweeps in batched launches: each launch covers up to a few
+ * dozen members, and its blocks are dealt member after member so small grids
+ * still fill the GPU.  The FP32 + refinement residual and update steps run
+ * per member.  Members are checked with exactly the rules lkp_solve applies
+ * (the group's sweeps per step playing the role of check_every), so a
+ * member's sweeps, answer and retirement are the same alone (lkp_solve with
+ * check_every = sweeps per step and the same velocity-group split) and in any
+ * mix.  Membership changes between steps; the caller retires converged
+ * members (lkp_get_phi, then lkp_group_remove or lkp_destroy).
+ * ------------------------------------------------------------------------ */
+typedef struct lkp_group lkp_group;
+
+typedef enum lkp_member_state {
+  LKP_MEMBER_RUNNING = 0,
+  LKP_MEMBER_CONVERGED = 1,
+  LKP_MEMBER_FAILED = 2     /* diverged, or max_sweeps reached: see status */
+} lkp_member_state;
+
+typedef struct lkp_member_report {
+  lkp_handle *handle;
+  int32_t state;            /* lkp_member_state */
+  int32_t status;           /* LKP_OK, or the error that stopped the member */
+  int64_t sweeps;           /* sweeps since the member was added */
+  int32_t outer;            /* refinement steps (F32_IR) */
+  int32_t reserved;
+  double est_rel_err;       /* estimated relative L2 distance to the fixed point */
+  double max_change;        /* max |Phi_t - Phi_{t-1}| at the last check (plain sweeps) */
+  double phi_l2;            /* ||Phi||_2 */
+} lkp_member_report;
+
+/* Create an empty group for (lattice, order, precision) on `stream`
+ * (hipStream_t; NULL = default).  The group owns only its bookkeeping. */
+lkp_status lkp_group_create(int32_t lattice, int32_t order, int32_t precision, void *stream,
+                            lkp_group **out);
+
+/* Admit a created handle of the group's class and stream, with its stopping
+ * options (tol_rel_l2 / tol_maxchange / max_sweeps as in lkp_solve; the
+ * group's sweeps per step replace check_every).  The handle's convergence
+ * state starts afresh; while resident it cannot be driven by lkp_solve or
+ * lkp_step.  Errors: LKP_ERR_ARG (class or stream mismatch, already in a
+ * group), LKP_ERR_STATE. */
+lkp_status lkp_group_add(lkp_group *g, lkp_handle *h, const lkp_solve_opts *o);
+
+/* Remove a member (its state and device memory stay with the handle). */
+lkp_status lkp_group_remove(lkp_group *g, lkp_handle *h);
+
+/* Advance every running member by `sweeps` (>= 2) sweeps with one check at
+ * the end, then report every member (running, converged or failed) into
+ * out[0 .. *count) (out may be NULL when capacity is 0).  Enqueues on the
+ * group's stream and synchronises it once for the read-back of all members'
+ * norms (48 bytes each). */
+lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, int32_t capacity,
+                          int32_t *count);
+
+/* Destroy the group; members are released from it, not destroyed. */
+lkp_status lkp_group_destroy(lkp_group *g);
 
 #ifdef __cplusplus
 }

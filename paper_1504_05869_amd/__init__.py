@@ -19,8 +19,8 @@ import torch
 from . import _lib
 from ._lib import LATTICES, PRECISIONS, LkpError, check
 
-__all__ = ["Problem", "lattice_info", "footprint_bytes", "LkpError", "LATTICES", "PRECISIONS",
-           "library_path"]
+__all__ = ["Problem", "Group", "lattice_info", "footprint_bytes", "LkpError", "LATTICES",
+           "PRECISIONS", "library_path", "solve_opts"]
 
 
 def library_path() -> str:
@@ -78,6 +78,19 @@ def lattice_info(lattice: str, order: int = 1) -> dict:
             "phi": ph[:Q].copy(), "chi": ch[:Q].copy(), "cs2": cs2.value}
 
 
+def solve_opts(tol_rel_l2=0.0, tol_maxchange=0.0, max_sweeps=10_000_000, check_every=100,
+               use_graph=True, max_outer=0, ir_inner_tol=0.0) -> _lib.SolveOpts:
+    o = _lib.SolveOpts()
+    o.tol_rel_l2 = float(tol_rel_l2)
+    o.tol_maxchange = float(tol_maxchange)
+    o.max_sweeps = int(max_sweeps)
+    o.check_every = int(check_every)
+    o.use_graph = int(bool(use_graph))
+    o.max_outer = int(max_outer)
+    o.ir_inner_tol = float(ir_inner_tol)
+    return o
+
+
 class Problem:
     """One resident periodic Poisson problem lap(Phi) = -s on the GPU."""
 
@@ -132,14 +145,8 @@ class Problem:
     def solve(self, tol_rel_l2: float = 0.0, tol_maxchange: float = 0.0,
               max_sweeps: int = 10_000_000, check_every: int = 100, use_graph: bool = True,
               max_outer: int = 0, ir_inner_tol: float = 0.0, raise_on_error: bool = True) -> dict:
-        o = _lib.SolveOpts()
-        o.tol_rel_l2 = float(tol_rel_l2)
-        o.tol_maxchange = float(tol_maxchange)
-        o.max_sweeps = int(max_sweeps)
-        o.check_every = int(check_every)
-        o.use_graph = int(bool(use_graph))
-        o.max_outer = int(max_outer)
-        o.ir_inner_tol = float(ir_inner_tol)
+        o = solve_opts(tol_rel_l2, tol_maxchange, max_sweeps, check_every, use_graph, max_outer,
+                       ir_inner_tol)
         r = _lib.SolveReport()
         st = self._lib.lkp_solve(self._h, ctypes.byref(o), ctypes.byref(r))
         rep = {f: getattr(r, f) for f, _ in _lib.SolveReport._fields_}
@@ -186,3 +193,56 @@ class Problem:
         d = {f: getattr(i, f) for f, _ in _lib.HandleInfo._fields_}
         d["n"] = tuple(i.n)
         return d
+
+
+class Group:
+    """Resident problems of one class advanced together in batched sweeps."""
+
+    def __init__(self, lattice: str, order: int, precision: str = "f64", stream=None):
+        self._lib = _lib.load()
+        self._g = ctypes.c_void_p()
+        self._stream = _stream_handle(stream)
+        self.lattice, self.order, self.precision = lattice, int(order), precision
+        check(self._lib.lkp_group_create(LATTICES[lattice], int(order), PRECISIONS[precision],
+                                         self._stream, ctypes.byref(self._g)), "lkp_group_create")
+        self._members = {}
+
+    def add(self, problem: Problem, tol_rel_l2=0.0, tol_maxchange=0.0, max_sweeps=10_000_000):
+        o = solve_opts(tol_rel_l2, tol_maxchange, max_sweeps)
+        check(self._lib.lkp_group_add(self._g, problem._h, ctypes.byref(o)), "lkp_group_add")
+        self._members[problem._h.value] = problem
+
+    def remove(self, problem: Problem):
+        check(self._lib.lkp_group_remove(self._g, problem._h), "lkp_group_remove")
+        self._members.pop(problem._h.value, None)
+
+    def __len__(self):
+        return len(self._members)
+
+    def step(self, sweeps: int) -> list:
+        """Advance every running member; returns one report dict per member."""
+        cap = max(1, len(self._members))
+        arr = (_lib.MemberReport * cap)()
+        n = ctypes.c_int32()
+        check(self._lib.lkp_group_step(self._g, int(sweeps), arr, cap, ctypes.byref(n)),
+              "lkp_group_step")
+        out = []
+        for k in range(min(n.value, cap)):
+            r = arr[k]
+            out.append({"problem": self._members.get(r.handle), "state": _lib.MEMBER_STATES[r.state],
+                        "status": _lib.STATUS.get(r.status, r.status), "sweeps": r.sweeps,
+                        "outer": r.outer, "est_rel_err": r.est_rel_err,
+                        "max_change": r.max_change, "phi_l2": r.phi_l2})
+        return out
+
+    def close(self):
+        if getattr(self, "_g", None) and self._g.value:
+            self._lib.lkp_group_destroy(self._g)
+            self._g = ctypes.c_void_p()
+            self._members.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,7 +19,10 @@ STATUS = {0: "LKP_OK", 1: "LKP_ERR_ARG", 2: "LKP_ERR_LATTICE_ORDER", 3: "LKP_ERR
           10: "LKP_ERR_UNSUPPORTED"}
 EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_solve", "lkp_step",
            "lkp_residual", "lkp_get_phi", "lkp_get_populations", "lkp_set_populations",
-           "lkp_lattice_info", "lkp_get_info", "lkp_sync", "lkp_last_error"]
+           "lkp_lattice_info", "lkp_get_info", "lkp_sync", "lkp_last_error",
+           "lkp_group_create", "lkp_group_add", "lkp_group_remove", "lkp_group_step",
+           "lkp_group_destroy"]
+MEMBER_STATES = {0: "running", 1: "converged", 2: "failed"}
 
 
 class ProblemDesc(ctypes.Structure):
@@ -63,6 +66,13 @@ class HandleInfo(ctypes.Structure):
                 ("footprint_bytes", ctypes.c_int64)]
 
 
+class MemberReport(ctypes.Structure):
+    _fields_ = [("handle", ctypes.c_void_p), ("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("sweeps", ctypes.c_int64), ("outer", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("est_rel_err", ctypes.c_double), ("max_change", ctypes.c_double),
+                ("phi_l2", ctypes.c_double)]
+
+
 _LIB = None
 
 
@@ -94,6 +104,13 @@ def load() -> ctypes.CDLL:
         "lkp_get_info": (ctypes.c_int, [H, P(HandleInfo)]),
         "lkp_sync": (ctypes.c_int, [H]),
         "lkp_last_error": (ctypes.c_char_p, []),
+        "lkp_group_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_void_p, P(H)]),
+        "lkp_group_add": (ctypes.c_int, [H, H, P(SolveOpts)]),
+        "lkp_group_remove": (ctypes.c_int, [H, H]),
+        "lkp_group_step": (ctypes.c_int, [H, ctypes.c_int32, P(MemberReport), ctypes.c_int32,
+                                          P(ctypes.c_int32)]),
+        "lkp_group_destroy": (ctypes.c_int, [H]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

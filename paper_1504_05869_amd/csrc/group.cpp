@@ -1,0 +1,336 @@
+// Serving ABI: a group of resident problems of one class advanced together
+// in batched sweeps (see include/lkp.h).  Host code only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lattices.hpp"
+#include "lkp.h"
+#include "runtime.hpp"
+
+using namespace lkp;
+using namespace lkp::rt;
+
+struct lkp_group {
+  int lattice = 0, order = 0, precision = 0, Q = 0;
+  int P = 1;
+  hipStream_t stream = nullptr;
+  std::vector<lkp_handle *> members;
+  double *norms_dev = nullptr;   // NUM_NORMS per member slot
+  double *norms_host = nullptr;  // pinned mirror
+  size_t cap = 0;
+
+  int mode() const {
+    return precision == LKP_F64 ? MODE_F64 : (precision == LKP_F32 ? MODE_F32 : MODE_INNER);
+  }
+};
+
+namespace {
+
+lkp_status ensure_norms(lkp_group *g, size_t n) {
+  if (n <= g->cap) return LKP_OK;
+  size_t c = std::max<size_t>(16, 2 * n);
+  if (g->norms_dev) LKP_HIP_TRY(hipFree(g->norms_dev));
+  if (g->norms_host) LKP_HIP_TRY(hipHostFree(g->norms_host));
+  g->norms_dev = nullptr;
+  g->norms_host = nullptr;
+  LKP_HIP_TRY(hipMalloc(&g->norms_dev, c * NUM_NORMS * sizeof(double)));
+  LKP_HIP_TRY(hipHostMalloc(&g->norms_host, c * NUM_NORMS * sizeof(double), hipHostMallocDefault));
+  g->cap = c;
+  return LKP_OK;
+}
+
+// One sweep of a member in a batched launch.
+struct Slot {
+  lkp_handle *h;
+  const void *fin;
+  void *fout;
+  const void *src;
+  const double *phi_prev;
+  double *phi_out;
+};
+
+template <int Q>
+lkp_status launch_slots(lkp_group *g, int flags, const std::vector<Slot> &slots) {
+  constexpr int cap = batch_capacity(Q);
+  BatchParams<Q> bp;
+  std::memset(&bp, 0, sizeof bp);
+  const lkp_handle *h0 = slots[0].h;
+  for (int i = 0; i < Q; ++i) {
+    bp.phi[i] = h0->phi[i];
+    bp.chi[i] = h0->chi[i];
+  }
+  const unsigned cells = cells_per_block(g->P);
+  for (size_t b = 0; b < slots.size(); b += cap) {
+    bp.nmembers = 0;
+    bp.nblocks = 0;
+    const size_t e = std::min(slots.size(), b + (size_t)cap);
+    for (size_t k = b; k < e; ++k) {
+      const Slot &s = slots[k];
+      BatchMember &m = bp.m[bp.nmembers++];
+      m.fin = s.fin;
+      m.fout = s.fout;
+      m.src = s.src;
+      m.om1 = 1.0 - s.h->omega;
+      m.omega = s.h->omega;
+      m.phi_prev = s.phi_prev;
+      m.phi_out = s.phi_out;
+      m.partials = s.h->partials;
+      m.nx = (unsigned)s.h->n[0];
+      m.ny = (unsigned)s.h->n[1];
+      m.nz = (unsigned)s.h->n[2];
+      m.ncells = s.h->ncells;
+      m.plane = s.h->ncells;
+      m.simple_wrap = s.h->simple_wrap ? 1u : 0u;
+      m.nblocks = (s.h->ncells + cells - 1) / cells;
+      m.block_begin = bp.nblocks;
+      bp.nblocks += m.nblocks;
+    }
+    hipError_t err = launch_sweep_batch(g->lattice, g->mode(), g->P, flags, &bp, g->stream);
+    if (err != hipSuccess) return fail(LKP_ERR_HIP, "batched sweep launch: %s", hipGetErrorString(err));
+  }
+  return LKP_OK;
+}
+
+lkp_status launch_batched(lkp_group *g, int flags, const std::vector<Slot> &slots) {
+  if (slots.empty()) return LKP_OK;
+  switch (g->Q) {
+    case 5: return launch_slots<5>(g, flags, slots);
+    case 9: return launch_slots<9>(g, flags, slots);
+    case 13: return launch_slots<13>(g, flags, slots);
+    case 25: return launch_slots<25>(g, flags, slots);
+    case 81: return launch_slots<81>(g, flags, slots);
+    case 111: return launch_slots<111>(g, flags, slots);
+    case 169: return launch_slots<169>(g, flags, slots);
+  }
+  return fail(LKP_ERR_UNSUPPORTED, "no batched sweep for Q = %d", g->Q);
+}
+
+lkp_status read_slots(lkp_group *g, size_t n) {
+  if (n == 0) return LKP_OK;
+  LKP_HIP_TRY(hipMemcpyAsync(g->norms_host, g->norms_dev, n * NUM_NORMS * sizeof(double),
+                             hipMemcpyDeviceToHost, g->stream));
+  LKP_HIP_TRY(hipStreamSynchronize(g->stream));
+  return LKP_OK;
+}
+
+void set_failed(lkp_handle *h, lkp_status st) {
+  h->gstate = LKP_MEMBER_FAILED;
+  h->grep.status = st;
+}
+
+// K plain sweeps (F64 / F32) of every member, norms on the last two.
+lkp_status step_plain(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
+  std::vector<int> cur(run.size());
+  for (size_t k = 0; k < run.size(); ++k) cur[k] = run[k]->cur;
+  std::vector<Slot> slots(run.size());
+  for (int j = 0; j < K; ++j) {
+    int flags = 0;
+    if (j == K - 2) flags = FLAG_PHI;
+    if (j == K - 1) flags = FLAG_REDUCE;
+    for (size_t k = 0; k < run.size(); ++k) {
+      lkp_handle *h = run[k];
+      Slot &s = slots[k];
+      s.h = h;
+      s.fin = h->f[cur[k]];
+      s.fout = h->f[1 - cur[k]];
+      s.src = h->S;
+      s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
+      s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
+      cur[k] = 1 - cur[k];
+    }
+    if (lkp_status st = launch_batched(g, flags, slots)) return st;
+  }
+  for (size_t k = 0; k < run.size(); ++k)
+    if (lkp_status st = finish_norms(run[k], sweep_blocks(run[k], g->P),
+                                     g->norms_dev + k * NUM_NORMS, g->stream))
+      return st;
+  if (lkp_status st = read_slots(g, run.size())) return st;
+  for (size_t k = 0; k < run.size(); ++k) {
+    lkp_handle *h = run[k];
+    commit_chunk(h, K);
+    h->g_sweeps += K;
+    bool conv = false;
+    const bool prev_ok = h->total_sweeps >= 2;
+    lkp_status st = track_check(h, g->norms_host + k * NUM_NORMS, prev_ok, h->gopts, &h->grep, &conv);
+    if (st != LKP_OK) {
+      set_failed(h, st);
+    } else if (conv) {
+      h->gstate = LKP_MEMBER_CONVERGED;
+    } else if (h->g_sweeps >= h->gopts.max_sweeps) {
+      set_failed(h, fail(LKP_ERR_NOT_CONVERGED, "member reached max_sweeps"));
+    }
+  }
+  return LKP_OK;
+}
+
+// One refinement step round: residuals for members that need one, then K
+// batched inner sweeps for members inside an inner solve.
+lkp_status step_ir(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
+  std::vector<lkp_handle *> res;
+  for (lkp_handle *h : run)
+    if (h->ir.phase == IR_RESID) res.push_back(h);
+  for (size_t k = 0; k < res.size(); ++k)
+    if (lkp_status st = ir_launch_residual(res[k], g->norms_dev + k * NUM_NORMS)) return st;
+  if (lkp_status st = read_slots(g, res.size())) return st;
+  for (size_t k = 0; k < res.size(); ++k) {
+    lkp_handle *h = res[k];
+    h->g_sweeps += 1;
+    bool conv = false;
+    lkp_status st = ir_after_residual(h, g->norms_host + k * NUM_NORMS, h->gopts, &h->grep, &conv);
+    if (st != LKP_OK) set_failed(h, st);
+    else if (conv) h->gstate = LKP_MEMBER_CONVERGED;
+  }
+  std::vector<lkp_handle *> inner;
+  for (lkp_handle *h : run) {
+    if (h->gstate != LKP_MEMBER_RUNNING || h->ir.phase != IR_INNER) continue;
+    if (h->g_sweeps >= h->gopts.max_sweeps) {
+      set_failed(h, fail(LKP_ERR_NOT_CONVERGED, "member reached max_sweeps"));
+      continue;
+    }
+    inner.push_back(h);
+  }
+  std::vector<Slot> slots(inner.size());
+  for (int j = 0; j < K; ++j) {
+    int flags = 0;
+    if (j == K - 2) flags = FLAG_PHI;
+    if (j == K - 1) flags = FLAG_REDUCE;
+    for (size_t k = 0; k < inner.size(); ++k) {
+      lkp_handle *h = inner[k];
+      Slot &s = slots[k];
+      s.h = h;
+      s.fin = h->d32[h->ir.dc];
+      s.fout = h->d32[1 - h->ir.dc];
+      s.src = h->r32;
+      s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
+      s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
+      h->ir.dc = 1 - h->ir.dc;
+    }
+    if (lkp_status st = launch_batched(g, flags, slots)) return st;
+  }
+  for (size_t k = 0; k < inner.size(); ++k)
+    if (lkp_status st = finish_norms(inner[k], sweep_blocks(inner[k], g->P),
+                                     g->norms_dev + k * NUM_NORMS, g->stream))
+      return st;
+  if (lkp_status st = read_slots(g, inner.size())) return st;
+  for (size_t k = 0; k < inner.size(); ++k) {
+    lkp_handle *h = inner[k];
+    h->total_sweeps += K;
+    h->g_sweeps += K;
+    lkp_status st = ir_after_inner(h, g->norms_host + k * NUM_NORMS, K, h->gopts, &h->grep);
+    if (st != LKP_OK) set_failed(h, st);
+  }
+  return LKP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lkp_status lkp_group_create(int32_t lattice, int32_t order, int32_t precision, void *stream,
+                            lkp_group **out) {
+  if (!out) return fail(LKP_ERR_ARG, "null output group pointer");
+  *out = nullptr;
+  if (lattice < 0 || lattice >= LKP_NUM_LATTICES) return fail(LKP_ERR_ARG, "unknown lattice");
+  if (precision < LKP_F64 || precision > LKP_F32_IR) return fail(LKP_ERR_ARG, "unknown precision");
+  const VelTable T = velocity_table(lattice);
+  if (order > T.max_order || (order != 1 && order != 3 && order != 5 && order != 7))
+    return fail(LKP_ERR_LATTICE_ORDER, "order %d not available on this lattice", order);
+  lkp_group *g = new lkp_group();
+  g->lattice = lattice;
+  g->order = order;
+  g->precision = precision;
+  g->Q = T.q;
+  g->stream = (hipStream_t)stream;
+  g->P = default_split(g->Q, g->mode());
+  if (const char *env = std::getenv("LKP_SPLIT")) {
+    const int P = std::atoi(env);
+    if (sweep_variant_available(lattice, g->mode(), P)) g->P = P;
+  }
+  *out = g;
+  return LKP_OK;
+}
+
+lkp_status lkp_group_add(lkp_group *g, lkp_handle *h, const lkp_solve_opts *o) {
+  if (!g || !h || !o) return fail(LKP_ERR_ARG, "lkp_group_add: null argument");
+  if (h->group) return fail(LKP_ERR_ARG, "handle is already in a group");
+  if (h->lattice != g->lattice || h->order != g->order || h->precision != g->precision)
+    return fail(LKP_ERR_ARG, "handle class (lattice, order, precision) differs from the group's");
+  if (h->stream != g->stream) return fail(LKP_ERR_ARG, "handle stream differs from the group's");
+  if (!(o->tol_rel_l2 > 0) && !(o->tol_maxchange > 0))
+    return fail(LKP_ERR_ARG, "give tol_rel_l2 or tol_maxchange");
+  if (h->precision == LKP_F32_IR && !(o->tol_rel_l2 > 0))
+    return fail(LKP_ERR_ARG, "F32_IR needs tol_rel_l2");
+  if (o->max_sweeps < 1) return fail(LKP_ERR_ARG, "max_sweeps must be >= 1");
+  if (lkp_status st = ensure_norms(g, g->members.size() + 1)) return st;
+  h->group = g;
+  h->gopts = *o;
+  h->grep = lkp_solve_report{};
+  h->gstate = LKP_MEMBER_RUNNING;
+  h->g_sweeps = 0;
+  h->trk = Tracker();
+  h->ir = IrState();
+  h->split = g->P;
+  h->tuned = true;
+  g->members.push_back(h);
+  return LKP_OK;
+}
+
+lkp_status lkp_group_remove(lkp_group *g, lkp_handle *h) {
+  if (!g || !h) return fail(LKP_ERR_ARG, "lkp_group_remove: null argument");
+  auto it = std::find(g->members.begin(), g->members.end(), h);
+  if (it == g->members.end()) return fail(LKP_ERR_ARG, "handle is not in this group");
+  g->members.erase(it);
+  h->group = nullptr;
+  return LKP_OK;
+}
+
+lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, int32_t capacity,
+                          int32_t *count) {
+  if (!g) return fail(LKP_ERR_ARG, "lkp_group_step: null group");
+  if (sweeps < 2) return fail(LKP_ERR_ARG, "lkp_group_step: sweeps must be >= 2");
+  if (capacity > 0 && !out) return fail(LKP_ERR_ARG, "lkp_group_step: null report array");
+  std::vector<lkp_handle *> run;
+  for (lkp_handle *h : g->members)
+    if (h->gstate == LKP_MEMBER_RUNNING) run.push_back(h);
+  if (!run.empty()) {
+    lkp_status st = g->precision == LKP_F32_IR ? step_ir(g, sweeps, run) : step_plain(g, sweeps, run);
+    if (st != LKP_OK) return st;
+  }
+  int32_t n = 0;
+  for (lkp_handle *h : g->members) {
+    if (n < capacity) {
+      lkp_member_report &r = out[n];
+      r.handle = h;
+      r.state = h->gstate;
+      r.status = h->gstate == LKP_MEMBER_FAILED ? h->grep.status : LKP_OK;
+      r.sweeps = h->g_sweeps;
+      r.outer = h->precision == LKP_F32_IR ? h->ir.outer : 0;
+      r.reserved = 0;
+      r.est_rel_err = h->grep.est_rel_err;
+      r.max_change = h->grep.max_change;
+      r.phi_l2 = h->grep.phi_l2;
+    }
+    ++n;
+  }
+  if (count) *count = n;
+  clear_error();
+  return LKP_OK;
+}
+
+lkp_status lkp_group_destroy(lkp_group *g) {
+  if (!g) return LKP_OK;
+  for (lkp_handle *h : g->members) h->group = nullptr;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  else (void)hipDeviceSynchronize();
+  if (g->norms_dev) (void)hipFree(g->norms_dev);
+  if (g->norms_host) (void)hipHostFree(g->norms_host);
+  delete g;
+  return LKP_OK;
+}
+
+}  // extern "C"

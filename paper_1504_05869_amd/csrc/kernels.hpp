@@ -37,16 +37,60 @@ struct SweepParams {
   const void *fin;        // Q planes, input precision of the mode
   void *fout;             // Q planes, output precision of the mode
   const void *src;        // S (n values) or r (Q planes) in the mode's source precision
-  const void *coef;       // compute precision: [omega phi_i]_Q, [chi_i]_Q
   double om1;             // 1 - omega
   const double *phi_prev; // previous sweep's Phi (FLAG_REDUCE; may be null)
   double *phi_out;        // this sweep's Phi (FLAG_PHI)
   double *partials;       // NUM_NORMS per block (FLAG_REDUCE)
   unsigned nx, ny, nz;
-  unsigned ncells;        // nx * ny * nz (< 2^31)
+  unsigned ncells;        // nx * ny * nz (< 2^29)
+  unsigned plane;         // elements between consecutive population planes (>= ncells)
   unsigned simple_wrap;   // 1 when every axis is at least its largest |v| component
   unsigned nblocks;       // grid size (set by the launcher)
+  // [omega phi_i]_Q then [chi_i]_Q in the mode's compute precision, passed by
+  // value so the kernel reads them from the constant argument segment
+  union {
+    double d[2 * MAXQ];
+    float f[2 * MAXQ];
+  } coef;
 };
+static_assert(sizeof(SweepParams) <= 4096, "kernel arguments are limited to 4 KiB");
+
+// One problem of a batched launch (same fields as SweepParams, no coefficients).
+struct BatchMember {
+  const void *fin;
+  void *fout;
+  const void *src;
+  double om1;             // 1 - omega
+  double omega;           // omega phi_i is formed in the kernel from the class-wide phi_i
+  const double *phi_prev;
+  double *phi_out;
+  double *partials;
+  unsigned nx, ny, nz;
+  unsigned ncells;
+  unsigned plane;         // elements between consecutive population planes
+  unsigned simple_wrap;
+  unsigned nblocks;       // this member's blocks
+  unsigned block_begin;   // first global block of this member
+};
+
+// Members per batched launch: the table and the class-wide phi_i, chi_i
+// (FP64) must fit the 4 KiB kernel-argument segment.
+constexpr int batch_capacity(int q) {
+  const int m = (4000 - 16 * q - 16) / (int)sizeof(BatchMember);
+  return m > 32 ? 32 : m;
+}
+
+template <int Q>
+struct BatchParams {
+  unsigned nmembers;
+  unsigned nblocks;  // total over members
+  BatchMember m[batch_capacity(Q)];
+  double phi[Q];
+  double chi[Q];
+};
+static_assert(sizeof(BatchParams<169>) <= 4096, "batched launch arguments exceed 4 KiB");
+static_assert(sizeof(BatchParams<111>) <= 4096, "batched launch arguments exceed 4 KiB");
+static_assert(sizeof(BatchParams<5>) <= 4096, "batched launch arguments exceed 4 KiB");
 
 // Cells one block covers for a velocity-group split P (256 threads = 4 waves;
 // P waves share one 64-cell column and each holds Q/P populations).
@@ -74,6 +118,13 @@ bool sweep_variant_available(int lattice, int mode, int P);
 // Per-lattice entry points, one translation unit each (sweep_<lattice>.hip).
 template <int LID>
 hipError_t launch_lattice_tu(int mode, int P, int flags, SweepParams p, hipStream_t s);
+
+template <int LID>
+hipError_t launch_batch_tu(int mode, int P, int flags, const void *bp, hipStream_t s);
+
+// Enqueue one batched sweep over bp (a BatchParams<Q> of the lattice, with
+// nmembers, nblocks and every member's block_begin / nblocks filled).
+hipError_t launch_sweep_batch(int lattice, int mode, int P, int flags, const void *bp, hipStream_t s);
 
 // Enqueue one sweep; fills p.nblocks.  Returns hipErrorInvalidValue for an
 // unbuilt variant.

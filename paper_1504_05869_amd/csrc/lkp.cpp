@@ -22,12 +22,30 @@
 
 #include "constants.hpp"
 #include "kernels.hpp"
+#include "runtime.hpp"
 
 using namespace lkp;
+using namespace lkp::rt;
+
+#define HIP_TRY LKP_HIP_TRY
+
+namespace lkp {
+namespace rt {
 
 namespace {
-
 thread_local std::string g_err;
+// Process-wide choice of the velocity-group split per (lattice, mode, size class).
+std::mutex g_tune_mu;
+std::map<long, int> g_tune;
+
+long tune_key(int lattice, int mode, int64_t ncells) {
+  int cls = 0;
+  while ((int64_t(1) << (2 * cls + 12)) < ncells && cls < 12) ++cls;
+  return ((long)lattice * 16 + mode) * 32 + cls;
+}
+}  // namespace
+
+const char *last_error() { return g_err.c_str(); }
 
 lkp_status fail(lkp_status st, const char *fmt, ...) {
   char buf[512];
@@ -39,26 +57,10 @@ lkp_status fail(lkp_status st, const char *fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                    \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(e_ == hipErrorOutOfMemory ? LKP_ERR_OOM : LKP_ERR_HIP, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                     \
-  } while (0)
+void clear_error() { g_err.clear(); }
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-// Process-wide choice of the velocity-group split per (lattice, mode, size class).
-std::mutex g_tune_mu;
-std::map<long, int> g_tune;
-
-long tune_key(int lattice, int mode, int64_t ncells) {
-  int cls = 0;
-  while ((int64_t(1) << (2 * cls + 12)) < ncells && cls < 12) ++cls;
-  return ((long)lattice * 16 + mode) * 32 + cls;
 }
 
 int default_split(int Q, int mode) {
@@ -68,48 +70,281 @@ int default_split(int Q, int mode) {
   return Q >= 169 ? 2 : 1;
 }
 
-}  // namespace
+unsigned sweep_blocks(const lkp_handle *h, int P) {
+  const unsigned c = cells_per_block(P);
+  return (h->ncells + c - 1) / c;
+}
 
-struct lkp_handle {
-  int lattice = 0, order = 0, dim = 0, precision = 0, Q = 0;
-  int64_t n[3] = {1, 1, 1};
-  unsigned ncells = 0;
-  double tau_lb = 0, omega = 0, cs2 = 0;
-  std::vector<double> w, phi, chi;
-  hipStream_t stream = nullptr;
-  hipStream_t capture = nullptr;  // private stream used only to record graphs
-  bool simple_wrap = true;
+void set_coefficients(const lkp_handle *h, int mode, SweepParams *p) {
+  const size_t n = h->c64.size();
+  if (mode == MODE_F32 || mode == MODE_INNER)
+    std::memcpy(p->coef.f, h->c32.data(), n * sizeof(float));
+  else
+    std::memcpy(p->coef.d, h->c64.data(), n * sizeof(double));
+}
 
-  // population state: F64 -> f[] double; F32 -> f[] float; F32_IR -> x (double) + d[] float
-  void *f[2] = {nullptr, nullptr};
-  int cur = 0;
-  void *S = nullptr;        // scaled source in the sweep precision (double for IR)
-  void *coef = nullptr;     // sweep precision coefficients
-  void *coef32 = nullptr;   // IR inner coefficients (float)
-  double *phi_dev = nullptr;  // phi_i on device (IR mass projection)
-  float *r32 = nullptr;       // IR residual
-  float *d32[2] = {nullptr, nullptr};
-  double *phib[2] = {nullptr, nullptr};
-  int64_t phi_sweep[2] = {-1, -1};
-  int phi_last = 1;
-  double *partials = nullptr;
-  size_t partial_cap = 0;
-  double *norms_dev = nullptr;
-  double *norms_host = nullptr;  // pinned
-  int64_t total_sweeps = 0;
-  int64_t footprint = 0;
-  int split = 1;
-  bool tuned = false;
-  std::map<long, hipGraphExec_t> graphs;
+SweepParams base_params(const lkp_handle *h) {
+  SweepParams p{};
+  p.om1 = 1.0 - h->omega;
+  p.nx = (unsigned)h->n[0];
+  p.ny = (unsigned)h->n[1];
+  p.nz = (unsigned)h->n[2];
+  p.ncells = h->ncells;
+  p.plane = h->ncells;
+  p.simple_wrap = h->simple_wrap ? 1u : 0u;
+  return p;
+}
 
-  int mode() const { return precision == LKP_F64 ? MODE_F64 : MODE_F32; }
-};
+lkp_status finish_norms(lkp_handle *h, unsigned nblocks, double *dst_dev, hipStream_t s) {
+  hipError_t e = launch_finish(h->partials, nblocks, dst_dev, s);
+  if (e != hipSuccess) return fail(LKP_ERR_HIP, "finish launch: %s", hipGetErrorString(e));
+  return LKP_OK;
+}
+
+void commit_chunk(lkp_handle *h, int k) {
+  const int64_t t0 = h->total_sweeps;
+  if (k % 2) h->cur = 1 - h->cur;
+  if (k >= 2) {
+    h->phi_sweep[0] = t0 + k - 1;
+    h->phi_sweep[1] = t0 + k;
+    h->phi_last = 1;
+  } else {
+    h->phi_last = 1 - h->phi_last;
+    h->phi_sweep[h->phi_last] = t0 + 1;
+  }
+  h->total_sweeps = t0 + k;
+}
+
+lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
+                       const lkp_solve_opts &o, lkp_solve_report *rep, bool *converged) {
+  *converged = false;
+  Tracker &t = h->trk;
+  if (nr[NORM_BAD] > 0)
+    return fail(LKP_ERR_DIVERGED, "non-finite values after %lld sweeps", (long long)h->total_sweeps);
+  rep->max_change = nr[NORM_MAX_DPHI];
+  rep->l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
+  rep->phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
+  rep->mass = nr[NORM_SUM_PHI];
+  if (!prev_ok) return LKP_OK;
+  const double l2 = rep->l2_change;
+  if (t.l2_prev > 0 && l2 > 0 && h->total_sweeps > t.t_prev) {
+    t.rate = std::pow(l2 / t.l2_prev, 1.0 / (double)(h->total_sweeps - t.t_prev));
+    rep->rate = t.rate;
+  }
+  if (l2 > 0) t.min_l2 = std::min(t.min_l2, l2);
+  if (l2 > 1e10 * t.min_l2 && l2 > 1e-300)
+    return fail(LKP_ERR_DIVERGED, "change grew by 1e10 (unstable tau_lb?)");
+  if (o.tol_maxchange > 0 && rep->max_change < o.tol_maxchange) *converged = true;
+  if (o.tol_rel_l2 > 0) {
+    if (l2 == 0) {
+      rep->est_rel_err = 0;
+      *converged = true;
+    } else if (t.rate > 0 && t.rate < 1 && rep->phi_l2 > 0) {
+      rep->est_rel_err = l2 * t.rate / (1 - t.rate) / rep->phi_l2;
+      if (rep->est_rel_err <= o.tol_rel_l2) *converged = true;
+    } else {
+      rep->est_rel_err = INFINITY;
+    }
+  }
+  t.l2_prev = l2;
+  t.t_prev = h->total_sweeps;
+  return LKP_OK;
+}
+
+// ---------------------------------------------------------------- F32 + IR
+//
+// x (FP64 population state) is refined by corrections d that solve
+// (I - T) d = r with r = T x + g - x, where T is one sweep without source and
+// g = chi_i S its source term.  r is formed in FP64 arithmetic on the GPU and
+// stored in FP32; d is iterated in FP32 (d <- T d + r) from d = 0; then
+// x += d - phi_i mean(d) in FP64, which keeps the mass mode (the eigenvector
+// phi_i of T with eigenvalue 1) at the zero of the initial state.
+
+lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
+  const int P = default_split(h->Q, MODE_RESID);
+  SweepParams p = base_params(h);
+  p.fin = h->f[0];
+  p.fout = h->r32;
+  p.src = h->S;
+  set_coefficients(h, MODE_RESID, &p);
+  p.phi_prev = nullptr;
+  p.phi_out = h->phib[1];
+  p.partials = h->partials;
+  hipError_t e = launch_sweep(h->lattice, MODE_RESID, P, FLAG_REDUCE, p, h->stream);
+  if (e != hipSuccess) return fail(LKP_ERR_HIP, "residual sweep launch: %s", hipGetErrorString(e));
+  h->total_sweeps += 1;  // one FP64 sweep of x
+  h->phi_last = 1;
+  h->phi_sweep[1] = h->total_sweeps;  // Phi of the refined state
+  return finish_norms(h, sweep_blocks(h, P), dst_dev, h->stream);
+}
+
+lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lkp_solve_opts &o,
+                             lkp_solve_report *rep, bool *converged) {
+  IrState &s = h->ir;
+  *converged = false;
+  s.rnorm = std::sqrt(nr[NORM_SUM_R2]);
+  const double phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
+  rep->phi_l2 = phi_l2;
+  rep->mass = nr[NORM_SUM_PHI];
+  rep->outer = s.outer;
+  if (nr[NORM_BAD] > 0) return fail(LKP_ERR_DIVERGED, "non-finite residual");
+  if (s.corr_prev >= 0 && s.rnorm_prev > 0 && phi_l2 > 0) {
+    // the last correction scaled by how much the residual shrank since it
+    rep->est_rel_err = s.corr_prev * (s.rnorm / s.rnorm_prev) / phi_l2;
+    s.est = rep->est_rel_err;
+    if (rep->est_rel_err <= o.tol_rel_l2) *converged = true;
+  }
+  if (s.rnorm == 0) {
+    rep->est_rel_err = 0;
+    *converged = true;
+  }
+  if (*converged) {
+    s.phase = IR_DONE;
+    return LKP_OK;
+  }
+  const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
+  if (s.outer >= max_outer) return fail(LKP_ERR_NOT_CONVERGED, "refinement: %d outer steps", s.outer);
+  // start the inner solve from d = 0
+  const size_t QN = (size_t)h->Q * h->ncells;
+  LKP_HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
+  s.dc = 0;
+  // Inner accuracy: as asked, or just enough to close the remaining gap
+  // (30 % margin), never below the FP32 sweep's own floor (~1e-7 relative).
+  if (o.ir_inner_tol > 0) {
+    s.inner_tol = o.ir_inner_tol;
+  } else {
+    const double want = s.est > 0 ? 0.3 * o.tol_rel_l2 / s.est : 1e-1;
+    s.inner_tol = std::min(1e-1, std::max(1e-7, want));
+  }
+  s.l2_prev = -1;
+  s.best_l2 = 1e300;
+  s.stall = 0;
+  s.t_in = 0;
+  s.t_prev = 0;
+  s.phase = IR_INNER;
+  return LKP_OK;
+}
+
+SweepParams ir_inner_params(lkp_handle *h, int P) {
+  SweepParams p = base_params(h);
+  p.fin = h->d32[h->ir.dc];
+  p.fout = h->d32[1 - h->ir.dc];
+  p.src = h->r32;
+  set_coefficients(h, MODE_INNER, &p);
+  p.partials = h->partials;
+  (void)P;
+  return p;
+}
+
+lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
+                          const lkp_solve_opts &o, lkp_solve_report *rep) {
+  IrState &s = h->ir;
+  if (nr[NORM_BAD] > 0) return fail(LKP_ERR_DIVERGED, "non-finite inner sweep");
+  s.t_in += K;
+  const double l2 = std::sqrt(nr[NORM_SUM_DPHI2]);
+  s.corr = std::sqrt(nr[NORM_SUM_PHI2]);
+  if (s.l2_prev > 0 && l2 > 0) {
+    const double r = std::pow(l2 / s.l2_prev, 1.0 / (double)(s.t_in - s.t_prev));
+    if (r < 1) s.rate = r;
+  }
+  s.stall = (l2 < 0.95 * s.best_l2) ? 0 : s.stall + 1;
+  s.best_l2 = std::min(s.best_l2, l2);
+  s.l2_prev = l2;
+  s.t_prev = s.t_in;
+  rep->rate = s.rate;
+  const double est = (s.rate > 0 && s.rate < 1) ? l2 * s.rate / (1 - s.rate) : 1e300;
+  if (!(s.corr == 0 || est <= s.inner_tol * s.corr || s.stall >= 3)) return LKP_OK;
+  // inner solve done: x += d - phi_i mean(d), FP64
+  const size_t QN = (size_t)h->Q * h->ncells;
+  unsigned nb = 0;
+  LKP_HIP_TRY(launch_sum_f32(h->d32[s.dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream));
+  LKP_HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
+  LKP_HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[s.dc], h->phi_dev, h->norms_dev, h->Q,
+                               h->ncells, h->stream));
+  s.outer += 1;
+  s.corr_prev = s.corr;
+  s.rnorm_prev = s.rnorm;
+  s.phase = IR_RESID;
+  rep->outer = s.outer;
+  return LKP_OK;
+}
+
+// Pick the velocity-group split by timing each built candidate on the
+// handle's own buffers.  Sweeps read f[cur] and write f[1-cur] without
+// swapping, so the state is unchanged.
+lkp_status tune_split(lkp_handle *h) {
+  if (h->tuned) return LKP_OK;
+  h->tuned = true;
+  const int mode = h->precision == LKP_F32_IR ? MODE_INNER : h->mode();
+  const long key = tune_key(h->lattice, mode, h->ncells);
+  // LKP_SPLIT forces a split when that variant is built (tests, experiments)
+  if (const char *env = std::getenv("LKP_SPLIT")) {
+    const int P = std::atoi(env);
+    if (sweep_variant_available(h->lattice, mode, P)) {
+      h->split = P;
+      return LKP_OK;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      h->split = it->second;
+      return LKP_OK;
+    }
+  }
+  const char *off = std::getenv("LKP_AUTOTUNE");
+  if ((off && std::atoi(off) == 0) || h->ncells < 4096 || h->precision == LKP_F32_IR) {
+    h->split = default_split(h->Q, mode);
+    return LKP_OK;
+  }
+  auto sweep_once = [&](int P) -> lkp_status {
+    SweepParams p = base_params(h);
+    p.fin = h->f[h->cur];
+    p.fout = h->f[1 - h->cur];
+    p.src = h->S;
+    set_coefficients(h, mode, &p);
+    hipError_t e = launch_sweep(h->lattice, mode, P, 0, p, h->stream);
+    if (e != hipSuccess) return fail(LKP_ERR_HIP, "tuning sweep: %s", hipGetErrorString(e));
+    return LKP_OK;
+  };
+  hipEvent_t e0, e1;
+  LKP_HIP_TRY(hipEventCreate(&e0));
+  LKP_HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bestP = default_split(h->Q, mode);
+  const int saved = h->split;
+  for (int P : {1, 2, 4}) {
+    if (!sweep_variant_available(h->lattice, mode, P)) continue;
+    h->split = P;
+    if (lkp_status st = sweep_once(P)) {
+      h->split = saved;
+      return st;
+    }
+    LKP_HIP_TRY(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < 3; ++r)
+      if (lkp_status st = sweep_once(P)) return st;
+    LKP_HIP_TRY(hipEventRecord(e1, h->stream));
+    LKP_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    LKP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bestP = P;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->split = bestP;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = bestP;
+  return LKP_OK;
+}
+
+}  // namespace rt
+}  // namespace lkp
 
 namespace {
-
-size_t pop_bytes(const lkp_handle &h) {
-  return (size_t)h.Q * h.ncells * (h.precision == LKP_F64 ? 8 : 4);
-}
 
 int64_t footprint_of(int precision, int Q, int64_t ncells) {
   const int64_t nb = (ncells + 63) / 64 + 8;
@@ -139,7 +374,8 @@ lkp_status validate(const lkp_problem_desc *d, LatticeConstants *lc, double *tau
     if (d->n[a] < 1) return fail(LKP_ERR_ARG, "n[%d] = %lld < 1", a, (long long)d->n[a]);
     if (a >= d->dim && d->n[a] != 1) return fail(LKP_ERR_ARG, "n[%d] must be 1 for dim %d", a, d->dim);
     cells *= d->n[a];
-    if (cells >= (int64_t(1) << 31)) return fail(LKP_ERR_ARG, "grid too large (>= 2^31 cells)");
+    // each population plane must stay below 4 GiB in FP64 (32-bit byte offsets)
+    if (cells >= (int64_t(1) << 29)) return fail(LKP_ERR_ARG, "grid too large (>= 2^29 cells)");
   }
   if (!lattice_constants(d->lattice, lc)) return fail(LKP_ERR_HIP, "lattice constant solve failed");
   double tau = d->tau_lb;
@@ -167,17 +403,6 @@ lkp_status ensure_partials(lkp_handle *h, size_t nblocks) {
   return LKP_OK;
 }
 
-SweepParams base_params(const lkp_handle *h) {
-  SweepParams p{};
-  p.om1 = 1.0 - h->omega;
-  p.nx = (unsigned)h->n[0];
-  p.ny = (unsigned)h->n[1];
-  p.nz = (unsigned)h->n[2];
-  p.ncells = h->ncells;
-  p.simple_wrap = h->simple_wrap ? 1u : 0u;
-  return p;
-}
-
 // One population sweep of the handle's own state (F64 / F32) from buffer
 // `in` to buffer `out` with `flags`.
 lkp_status enqueue_sweep(lkp_handle *h, hipStream_t s, int in, int out, int flags,
@@ -186,7 +411,7 @@ lkp_status enqueue_sweep(lkp_handle *h, hipStream_t s, int in, int out, int flag
   p.fin = h->f[in];
   p.fout = h->f[out];
   p.src = h->S;
-  p.coef = h->coef;
+  set_coefficients(h, h->mode(), &p);
   p.phi_prev = phi_prev;
   p.phi_out = phi_out;
   p.partials = h->partials;
@@ -195,9 +420,7 @@ lkp_status enqueue_sweep(lkp_handle *h, hipStream_t s, int in, int out, int flag
   return LKP_OK;
 }
 
-lkp_status read_norms(lkp_handle *h, unsigned nblocks, double out[NUM_NORMS]) {
-  hipError_t e = launch_finish(h->partials, nblocks, h->norms_dev, h->stream);
-  if (e != hipSuccess) return fail(LKP_ERR_HIP, "finish launch: %s", hipGetErrorString(e));
+lkp_status read_back(lkp_handle *h, double out[NUM_NORMS]) {
   HIP_TRY(hipMemcpyAsync(h->norms_host, h->norms_dev, NUM_NORMS * sizeof(double),
                          hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -205,9 +428,13 @@ lkp_status read_norms(lkp_handle *h, unsigned nblocks, double out[NUM_NORMS]) {
   return LKP_OK;
 }
 
-unsigned sweep_blocks(const lkp_handle *h, int P) {
-  const unsigned c = cells_per_block(P);
-  return (h->ncells + c - 1) / c;
+lkp_status read_norms(lkp_handle *h, unsigned nblocks, double out[NUM_NORMS]) {
+  if (lkp_status st = finish_norms(h, nblocks, h->norms_dev, h->stream)) return st;
+  HIP_TRY(hipMemcpyAsync(h->norms_host, h->norms_dev, NUM_NORMS * sizeof(double),
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  std::memcpy(out, h->norms_host, NUM_NORMS * sizeof(double));
+  return LKP_OK;
 }
 
 // Enqueue a chunk of k >= 1 sweeps whose last sweep reduces norms (and, for
@@ -231,20 +458,6 @@ lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
     cur = 1 - cur;
   }
   return LKP_OK;
-}
-
-void commit_chunk(lkp_handle *h, int k) {
-  const int64_t t0 = h->total_sweeps;
-  if (k % 2) h->cur = 1 - h->cur;
-  if (k >= 2) {
-    h->phi_sweep[0] = t0 + k - 1;
-    h->phi_sweep[1] = t0 + k;
-    h->phi_last = 1;
-  } else {
-    h->phi_last = 1 - h->phi_last;
-    h->phi_sweep[h->phi_last] = t0 + 1;
-  }
-  h->total_sweeps = t0 + k;
 }
 
 lkp_status run_chunk(lkp_handle *h, int k, bool use_graph) {
@@ -281,89 +494,17 @@ void drop_graphs(lkp_handle *h) {
   h->graphs.clear();
 }
 
-// Pick the velocity-group split by timing each built candidate on the
-// handle's own buffers.  Sweeps read f[cur] and write f[1-cur] without
-// swapping, so the state is unchanged.
-lkp_status tune_split(lkp_handle *h) {
-  if (h->tuned) return LKP_OK;
-  h->tuned = true;
-  const int mode = h->precision == LKP_F32_IR ? MODE_INNER : h->mode();
-  const long key = tune_key(h->lattice, mode, h->ncells);
-  // LKP_SPLIT forces a split when that variant is built (tests, experiments)
-  if (const char *env = std::getenv("LKP_SPLIT")) {
-    const int P = std::atoi(env);
-    if (sweep_variant_available(h->lattice, mode, P)) {
-      h->split = P;
-      return LKP_OK;
-    }
-  }
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
-      h->split = it->second;
-      return LKP_OK;
-    }
-  }
-  const char *off = std::getenv("LKP_AUTOTUNE");
-  if ((off && std::atoi(off) == 0) || h->ncells < 4096 || h->precision == LKP_F32_IR) {
-    h->split = default_split(h->Q, mode);
-    return LKP_OK;
-  }
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  float best = 1e30f;
-  int bestP = default_split(h->Q, mode);
-  const int saved = h->split;
-  for (int P : {1, 2, 4}) {
-    if (!sweep_variant_available(h->lattice, mode, P)) continue;
-    h->split = P;
-    if (lkp_status st = enqueue_sweep(h, h->stream, h->cur, 1 - h->cur, 0, nullptr, nullptr)) {
-      h->split = saved;
-      return st;
-    }
-    HIP_TRY(hipEventRecord(e0, h->stream));
-    for (int r = 0; r < 3; ++r)
-      if (lkp_status st = enqueue_sweep(h, h->stream, h->cur, 1 - h->cur, 0, nullptr, nullptr))
-        return st;
-    HIP_TRY(hipEventRecord(e1, h->stream));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      bestP = P;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  h->split = bestP;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[key] = bestP;
-  return LKP_OK;
-}
-
 lkp_status upload_coefficients(lkp_handle *h) {
   const int Q = h->Q;
-  std::vector<double> c64(2 * Q);
-  std::vector<float> c32(2 * Q);
+  h->c64.assign(2 * Q, 0.0);
+  h->c32.assign(2 * Q, 0.0f);
   for (int i = 0; i < Q; ++i) {
-    c64[i] = h->omega * h->phi[i];
-    c64[Q + i] = h->chi[i];
-    c32[i] = (float)c64[i];
-    c32[Q + i] = (float)h->chi[i];
-  }
-  if (h->precision == LKP_F32) {
-    HIP_TRY(hipMalloc(&h->coef, 2 * Q * sizeof(float)));
-    HIP_TRY(hipMemcpy(h->coef, c32.data(), 2 * Q * sizeof(float), hipMemcpyHostToDevice));
-  } else {
-    HIP_TRY(hipMalloc(&h->coef, 2 * Q * sizeof(double)));
-    HIP_TRY(hipMemcpy(h->coef, c64.data(), 2 * Q * sizeof(double), hipMemcpyHostToDevice));
+    h->c64[i] = h->omega * h->phi[i];
+    h->c64[Q + i] = h->chi[i];
+    h->c32[i] = (float)h->c64[i];
+    h->c32[Q + i] = (float)h->chi[i];
   }
   if (h->precision == LKP_F32_IR) {
-    HIP_TRY(hipMalloc(&h->coef32, 2 * Q * sizeof(float)));
-    HIP_TRY(hipMemcpy(h->coef32, c32.data(), 2 * Q * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&h->phi_dev, Q * sizeof(double)));
     HIP_TRY(hipMemcpy(h->phi_dev, h->phi.data(), Q * sizeof(double), hipMemcpyHostToDevice));
   }
@@ -372,7 +513,7 @@ lkp_status upload_coefficients(lkp_handle *h) {
 
 void release(lkp_handle *h) {
   drop_graphs(h);
-  void *ptrs[] = {h->f[0], h->f[1], h->S, h->coef, h->coef32, h->phi_dev, h->r32, h->d32[0],
+  void *ptrs[] = {h->f[0], h->f[1], h->S, h->phi_dev, h->r32, h->d32[0],
                   h->d32[1], h->phib[0], h->phib[1], h->partials, h->norms_dev};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -480,133 +621,20 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   return LKP_OK;
 }
 
-// ---------------------------------------------------------------- F32 + IR
-
-// One sweep of the IR machinery.
-lkp_status ir_sweep(lkp_handle *h, int mode, const void *in, void *out, const void *src,
-                    int flags, const double *phi_prev, double *phi_out, int P) {
-  SweepParams p = base_params(h);
-  p.fin = in;
-  p.fout = out;
-  p.src = src;
-  p.coef = mode == MODE_INNER ? h->coef32 : h->coef;
-  p.phi_prev = phi_prev;
-  p.phi_out = phi_out;
-  p.partials = h->partials;
-  hipError_t e = launch_sweep(h->lattice, mode, P, flags, p, h->stream);
-  if (e != hipSuccess) return fail(LKP_ERR_HIP, "IR sweep launch: %s", hipGetErrorString(e));
-  return LKP_OK;
-}
-
-// r = T x + g - x in FP64 arithmetic; Phi(x) into phib[1].  Returns norms.
-lkp_status ir_residual(lkp_handle *h, double norms[NUM_NORMS]) {
-  const int P = default_split(h->Q, MODE_RESID);
-  if (lkp_status st = ir_sweep(h, MODE_RESID, h->f[0], h->r32, h->S, FLAG_REDUCE, nullptr,
-                               h->phib[1], P))
-    return st;
-  h->phi_last = 1;
-  h->phi_sweep[1] = h->total_sweeps;  // Phi of the refined state
-  return read_norms(h, sweep_blocks(h, P), norms);
-}
-
-lkp_status solve_ir(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *rep, int64_t *done) {
-  const int K = std::max(2, o->check_every);
-  const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
-  const double inner_tol = o->ir_inner_tol > 0 ? o->ir_inner_tol : 1e-4;
-  const size_t QN = (size_t)h->Q * h->ncells;
-  double nr[NUM_NORMS];
-  h->total_sweeps += 1;  // each FP64 residual evaluation is one sweep of x
-  *done += 1;
-  if (lkp_status st = ir_residual(h, nr)) return st;
-  double rnorm = std::sqrt(nr[NORM_SUM_R2]);
-  double corr_prev = -1, rnorm_prev = -1;
-  int outer = 0;
-  double rate = 0;
-  for (;;) {
-    const double phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
-    rep->phi_l2 = phi_l2;
-    rep->mass = nr[NORM_SUM_PHI];
-    if (nr[NORM_BAD] > 0) return fail(LKP_ERR_DIVERGED, "non-finite residual");
-    if (corr_prev >= 0 && rnorm_prev > 0 && phi_l2 > 0) {
-      rep->est_rel_err = corr_prev * (rnorm / rnorm_prev) / phi_l2;
-      if (rep->est_rel_err <= o->tol_rel_l2) return LKP_OK;
-    }
-    if (rnorm == 0) {
-      rep->est_rel_err = 0;
-      return LKP_OK;
-    }
-    if (outer >= max_outer) return fail(LKP_ERR_NOT_CONVERGED, "refinement: %d outer steps", outer);
-    if (*done >= o->max_sweeps) return fail(LKP_ERR_NOT_CONVERGED, "refinement: max_sweeps");
-    // inner: d <- T d + r from d = 0, FP32
-    HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
-    int dc = 0;
-    double l2_prev = -1, corr = 0, best_l2 = 1e300;
-    int stall = 0;
-    int64_t t_prev = 0, t_in = 0;
-    const int P = h->split;
-    for (;;) {
-      for (int j = 0; j < K; ++j) {
-        int flags = 0;
-        double *po = nullptr;
-        const double *pp = nullptr;
-        if (j == K - 2) { flags = FLAG_PHI; po = h->phib[0]; }
-        if (j == K - 1) { flags = FLAG_REDUCE; pp = h->phib[0]; po = h->phib[1]; }
-        if (lkp_status st = ir_sweep(h, MODE_INNER, h->d32[dc], h->d32[1 - dc], h->r32, flags, pp,
-                                     po, P))
-          return st;
-        dc = 1 - dc;
-      }
-      t_in += K;
-      *done += K;
-      h->total_sweeps += K;
-      double ni[NUM_NORMS];
-      if (lkp_status st = read_norms(h, sweep_blocks(h, P), ni)) return st;
-      if (ni[NORM_BAD] > 0) return fail(LKP_ERR_DIVERGED, "non-finite inner sweep");
-      const double l2 = std::sqrt(ni[NORM_SUM_DPHI2]);
-      corr = std::sqrt(ni[NORM_SUM_PHI2]);
-      if (l2_prev > 0 && l2 > 0) {
-        const double r = std::pow(l2 / l2_prev, 1.0 / (double)(t_in - t_prev));
-        if (r < 1) rate = r;
-      }
-      stall = (l2 < 0.95 * best_l2) ? 0 : stall + 1;
-      best_l2 = std::min(best_l2, l2);
-      l2_prev = l2;
-      t_prev = t_in;
-      const double est = (rate > 0 && rate < 1) ? l2 * rate / (1 - rate) : 1e300;
-      if (corr == 0 || est <= inner_tol * corr || stall >= 3 || *done >= o->max_sweeps) break;
-    }
-    rep->rate = rate;
-    // x += d - phi_i * mean(d): FP64 accumulation with the mass mode removed
-    unsigned nb = 0;
-    HIP_TRY(launch_sum_f32(h->d32[dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream));
-    HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
-    HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[dc], h->phi_dev, h->norms_dev, h->Q,
-                             h->ncells, h->stream));
-    ++outer;
-    rep->outer = outer;
-    corr_prev = corr;
-    rnorm_prev = rnorm;
-    h->total_sweeps += 1;
-    *done += 1;
-    if (lkp_status st = ir_residual(h, nr)) return st;
-    rnorm = std::sqrt(nr[NORM_SUM_R2]);
-  }
-}
-
 }  // namespace
 
 // ================================================================== C ABI
 
 extern "C" {
 
-const char *lkp_last_error(void) { return g_err.c_str(); }
+const char *lkp_last_error(void) { return lkp::rt::last_error(); }
 
 int64_t lkp_footprint_bytes(const lkp_problem_desc *d) {
   LatticeConstants lc;
   double tau;
-  std::string keep = g_err;
+  const std::string keep = lkp::rt::last_error();
   if (validate(d, &lc, &tau) != LKP_OK) {
-    g_err = keep;
+    lkp::rt::fail(LKP_OK, "%s", keep.c_str());
     return 0;
   }
   return footprint_of(d->precision, lc.table.q, d->n[0] * d->n[1] * d->n[2]);
@@ -623,12 +651,13 @@ lkp_status lkp_create(const lkp_problem_desc *d, lkp_handle **out) {
     return st;
   }
   *out = h;
-  g_err.clear();
+  clear_error();
   return LKP_OK;
 }
 
 lkp_status lkp_destroy(lkp_handle *h) {
   if (!h) return LKP_OK;
+  if (h->group) lkp_group_remove(h->group, h);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   release(h);
@@ -641,6 +670,7 @@ lkp_status lkp_step(lkp_handle *h, int64_t sweeps) {
   if (sweeps == 0) return LKP_OK;
   if (h->precision == LKP_F32_IR)
     return fail(LKP_ERR_UNSUPPORTED, "lkp_step drives the plain sweep; F32_IR handles use lkp_solve");
+  if (h->group) return fail(LKP_ERR_STATE, "lkp_step: the handle is resident in a group");
   if (lkp_status st = tune_split(h)) return st;
   int cur = h->cur;
   for (int64_t j = 0; j < sweeps - 1; ++j) {
@@ -665,20 +695,53 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
     return fail(LKP_ERR_ARG, "lkp_solve: check_every and max_sweeps must be >= 1");
   if (!(o->tol_rel_l2 > 0) && !(o->tol_maxchange > 0))
     return fail(LKP_ERR_ARG, "lkp_solve: give tol_rel_l2 or tol_maxchange");
+  if (h->group) return fail(LKP_ERR_STATE, "lkp_solve: the handle is resident in a group");
   lkp_solve_report rep{};
   const double t_start = now_s();
-  int64_t done = 0;
+  const int64_t start = h->total_sweeps;
   lkp_status result = LKP_OK;
   if (lkp_status st = tune_split(h)) return st;
+  h->trk = Tracker();
 
   if (h->precision == LKP_F32_IR) {
     if (!(o->tol_rel_l2 > 0)) return fail(LKP_ERR_ARG, "F32_IR needs tol_rel_l2");
-    result = solve_ir(h, o, &rep, &done);
-  } else {
-    double l2_prev = -1, min_l2 = 1e300;
-    int64_t t_prev = -1;
+    // a resumed solve starts a fresh refinement from the current x
+    h->ir = IrState();
+    const int K = std::max(2, o->check_every);
     bool converged = false;
     while (!converged) {
+      double nr[NUM_NORMS];
+      if (h->ir.phase == IR_RESID) {
+        if (lkp_status st = ir_launch_residual(h, h->norms_dev)) return st;
+        if (lkp_status st = read_back(h, nr)) return st;
+        result = ir_after_residual(h, nr, *o, &rep, &converged);
+        if (result || converged) break;
+      }
+      if (h->total_sweeps - start >= o->max_sweeps) {
+        result = fail(LKP_ERR_NOT_CONVERGED, "refinement: max_sweeps reached");
+        break;
+      }
+      // one chunk of K inner FP32 sweeps, norms on the last two
+      const int P = h->split;
+      for (int j = 0; j < K; ++j) {
+        SweepParams p = ir_inner_params(h, P);
+        int flags = 0;
+        if (j == K - 2) { flags = FLAG_PHI; p.phi_out = h->phib[0]; }
+        if (j == K - 1) { flags = FLAG_REDUCE; p.phi_prev = h->phib[0]; p.phi_out = h->phib[1]; }
+        hipError_t e = launch_sweep(h->lattice, MODE_INNER, P, flags, p, h->stream);
+        if (e != hipSuccess) return fail(LKP_ERR_HIP, "inner sweep launch: %s", hipGetErrorString(e));
+        h->ir.dc = 1 - h->ir.dc;
+      }
+      h->total_sweeps += K;
+      if (lkp_status st = finish_norms(h, sweep_blocks(h, P), h->norms_dev, h->stream)) return st;
+      if (lkp_status st = read_back(h, nr)) return st;
+      result = ir_after_inner(h, nr, K, *o, &rep);
+      if (result) break;
+    }
+  } else {
+    bool converged = false;
+    while (!converged) {
+      const int64_t done = h->total_sweeps - start;
       if (done >= o->max_sweeps) {
         result = fail(LKP_ERR_NOT_CONVERGED, "no convergence in %lld sweeps",
                       (long long)o->max_sweeps);
@@ -687,55 +750,23 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
       const int k = (int)std::min<int64_t>(o->check_every, o->max_sweeps - done);
       // a one-sweep chunk compares with the previous sweep's Phi only if it exists
       const int a = h->phi_last;
-      const bool prev_ok =
-          k >= 2 ? (h->total_sweeps + k >= 2) : (h->phi_sweep[a] == h->total_sweeps && h->total_sweeps >= 1);
+      const bool prev_ok = k >= 2 ? (h->total_sweeps + k >= 2)
+                                  : (h->phi_sweep[a] == h->total_sweeps && h->total_sweeps >= 1);
       if (lkp_status st = run_chunk(h, k, o->use_graph != 0)) return st;
-      done += k;
       double nr[NUM_NORMS];
       if (lkp_status st = read_norms(h, sweep_blocks(h, h->split), nr)) return st;
-      if (nr[NORM_BAD] > 0) {
-        result = fail(LKP_ERR_DIVERGED, "non-finite values after %lld sweeps",
-                      (long long)h->total_sweeps);
-        break;
-      }
-      rep.max_change = nr[NORM_MAX_DPHI];
-      rep.l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
-      rep.phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
-      rep.mass = nr[NORM_SUM_PHI];
-      if (!prev_ok) continue;
-      const double l2 = rep.l2_change;
-      if (l2_prev > 0 && l2 > 0 && h->total_sweeps > t_prev) {
-        const double r = std::pow(l2 / l2_prev, 1.0 / (double)(h->total_sweeps - t_prev));
-        rep.rate = r;
-      }
-      if (l2 > 0) min_l2 = std::min(min_l2, l2);
-      if (l2 > 1e10 * min_l2 && l2 > 1e-300) {
-        result = fail(LKP_ERR_DIVERGED, "change grew by 1e10 (unstable tau_lb?)");
-        break;
-      }
-      if (o->tol_maxchange > 0 && rep.max_change < o->tol_maxchange) converged = true;
-      if (o->tol_rel_l2 > 0) {
-        if (l2 == 0) {
-          rep.est_rel_err = 0;
-          converged = true;
-        } else if (rep.rate > 0 && rep.rate < 1 && rep.phi_l2 > 0) {
-          rep.est_rel_err = l2 * rep.rate / (1 - rep.rate) / rep.phi_l2;
-          if (rep.est_rel_err <= o->tol_rel_l2) converged = true;
-        } else {
-          rep.est_rel_err = INFINITY;
-        }
-      }
-      l2_prev = l2;
-      t_prev = h->total_sweeps;
+      result = track_check(h, nr, prev_ok, *o, &rep, &converged);
+      if (result) break;
     }
   }
   rep.wall_s = now_s() - t_start;
-  rep.sweeps = done;
+  rep.sweeps = h->total_sweeps - start;
   rep.total_sweeps = h->total_sweeps;
-  rep.glups = rep.wall_s > 0 ? 1e-9 * (double)h->ncells * (double)done / rep.wall_s : 0;
+  rep.outer = h->precision == LKP_F32_IR ? h->ir.outer : 0;
+  rep.glups = rep.wall_s > 0 ? 1e-9 * (double)h->ncells * (double)rep.sweeps / rep.wall_s : 0;
   rep.status = result;
   if (rep_out) *rep_out = rep;
-  if (result == LKP_OK) g_err.clear();
+  if (result == LKP_OK) clear_error();
   return result;
 }
 
@@ -743,33 +774,24 @@ lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r) {
   if (!h || !r) return fail(LKP_ERR_ARG, "lkp_residual: null argument");
   std::memset(r, 0, sizeof *r);
   r->sweeps = h->total_sweeps;
-  if (h->precision == LKP_F32_IR) {
-    double nr[NUM_NORMS];
-    const int last = h->phi_last;
-    const int P = default_split(h->Q, MODE_RESID);
-    if (lkp_status st = ir_sweep(h, MODE_RESID, h->f[0], h->r32, h->S, FLAG_REDUCE,
-                                 h->phib[last], h->phib[1 - last], P))
-      return st;
-    if (lkp_status st = read_norms(h, sweep_blocks(h, P), nr)) return st;
-    r->max_change = nr[NORM_MAX_DPHI];
-    r->l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
-    r->pop_residual_l2 = std::sqrt(nr[NORM_SUM_R2]);
-    r->phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
-    r->mass = nr[NORM_SUM_PHI];
-    h->phi_sweep[1 - last] = -1;
-    return LKP_OK;
-  }
   const int last = h->phi_last;
   if (h->total_sweeps < 1 || h->phi_sweep[last] != h->total_sweeps)
     return fail(LKP_ERR_STATE, "lkp_residual needs the Phi of the last sweep (run a sweep first)");
   const int scratch = 1 - last;
   double nr[NUM_NORMS];
-  if (h->precision == LKP_F64) {
-    // FP64 residual: one sweep into the idle buffer (used as FP32 r storage)
+  if (h->precision == LKP_F64 || h->precision == LKP_F32_IR) {
+    // FP64 residual of the FP64 state; r goes to idle storage
     const int P = default_split(h->Q, MODE_RESID);
-    if (lkp_status st = ir_sweep(h, MODE_RESID, h->f[h->cur], h->f[1 - h->cur], h->S, FLAG_REDUCE,
-                                 h->phib[last], h->phib[scratch], P))
-      return st;
+    SweepParams p = base_params(h);
+    p.fin = h->precision == LKP_F64 ? h->f[h->cur] : h->f[0];
+    p.fout = h->precision == LKP_F64 ? h->f[1 - h->cur] : (void *)h->r32;
+    p.src = h->S;
+    set_coefficients(h, MODE_RESID, &p);
+    p.phi_prev = h->phib[last];
+    p.phi_out = h->phib[scratch];
+    p.partials = h->partials;
+    hipError_t e = launch_sweep(h->lattice, MODE_RESID, P, FLAG_REDUCE, p, h->stream);
+    if (e != hipSuccess) return fail(LKP_ERR_HIP, "residual launch: %s", hipGetErrorString(e));
     if (lkp_status st = read_norms(h, sweep_blocks(h, P), nr)) return st;
     r->pop_residual_l2 = std::sqrt(nr[NORM_SUM_R2]);
   } else {

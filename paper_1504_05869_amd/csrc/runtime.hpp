@@ -1,0 +1,136 @@
+// Internal runtime shared by the single-problem ABI (lkp.cpp) and the
+// batched serving ABI (group.cpp).  Host code only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lkp.h"
+
+namespace lkp {
+namespace rt {
+
+lkp_status fail(lkp_status st, const char *fmt, ...);
+void clear_error();
+const char *last_error();
+double now_s();
+
+#define LKP_HIP_TRY(expr)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return ::lkp::rt::fail(e_ == hipErrorOutOfMemory ? LKP_ERR_OOM : LKP_ERR_HIP,           \
+                             "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+
+// Convergence bookkeeping of one problem across checks (Sec. 4: the answer is
+// the steady state; the host estimates the distance to it from the one-sweep
+// change and the measured contraction per sweep).
+struct Tracker {
+  double l2_prev = -1.0;
+  double min_l2 = 1e300;
+  double rate = 0.0;
+  int64_t t_prev = -1;
+};
+
+// Iterative-refinement controller state of one F32_IR problem.
+enum IrPhase : int { IR_RESID = 0, IR_INNER = 1, IR_DONE = 2 };
+struct IrState {
+  int phase = IR_RESID;
+  int outer = 0;
+  double rnorm = -1.0, rnorm_prev = -1.0;
+  double corr = 0.0, corr_prev = -1.0;
+  double est = 1.0;           // estimated relative error of x (1 for x = 0)
+  double inner_tol = 1e-4;    // relative accuracy the current inner solve aims at
+  int dc = 0;                 // current inner correction buffer
+  double l2_prev = -1.0, best_l2 = 1e300, rate = 0.0;
+  int stall = 0;
+  int64_t t_in = 0, t_prev = 0;
+};
+
+}  // namespace rt
+}  // namespace lkp
+
+struct lkp_handle {
+  int lattice = 0, order = 0, dim = 0, precision = 0, Q = 0;
+  int64_t n[3] = {1, 1, 1};
+  unsigned ncells = 0;
+  double tau_lb = 0, omega = 0, cs2 = 0;
+  std::vector<double> w, phi, chi;
+  std::vector<double> c64;  // [omega phi_i]_Q, [chi_i]_Q (FP64 sweeps, residual)
+  std::vector<float> c32;   // the same rounded to FP32 (FP32 and IR inner sweeps)
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;  // private stream used only to record graphs
+  bool simple_wrap = true;
+
+  // population state: F64 -> f[] double; F32 -> f[] float; F32_IR -> f[0] = x
+  // (double) with d32[] the FP32 corrections and r32 the FP32 residual
+  void *f[2] = {nullptr, nullptr};
+  int cur = 0;
+  void *S = nullptr;          // scaled source in the sweep precision (double for IR)
+  double *phi_dev = nullptr;  // phi_i on the device (IR mass projection)
+  float *r32 = nullptr;
+  float *d32[2] = {nullptr, nullptr};
+  double *phib[2] = {nullptr, nullptr};
+  int64_t phi_sweep[2] = {-1, -1};
+  int phi_last = 1;
+  double *partials = nullptr;
+  size_t partial_cap = 0;
+  double *norms_dev = nullptr;
+  double *norms_host = nullptr;  // pinned
+  int64_t total_sweeps = 0;
+  int64_t footprint = 0;
+  int split = 1;
+  bool tuned = false;
+  std::map<long, hipGraphExec_t> graphs;
+
+  // convergence state (reset at lkp_solve entry and at lkp_group_add)
+  lkp::rt::Tracker trk;
+  lkp::rt::IrState ir;
+
+  // serving: the group this handle is resident in, its stopping options and
+  // progress since it was added
+  struct lkp_group *group = nullptr;
+  lkp_solve_opts gopts{};
+  lkp_solve_report grep{};
+  int gstate = 0;  // lkp_member_state
+  int64_t g_sweeps = 0;
+
+  int mode() const { return precision == LKP_F64 ? lkp::MODE_F64 : lkp::MODE_F32; }
+};
+
+namespace lkp {
+namespace rt {
+
+int default_split(int Q, int mode);
+unsigned sweep_blocks(const lkp_handle *h, int P);
+void set_coefficients(const lkp_handle *h, int mode, SweepParams *p);
+SweepParams base_params(const lkp_handle *h);
+lkp_status tune_split(lkp_handle *h);
+lkp_status finish_norms(lkp_handle *h, unsigned nblocks, double *dst_dev, hipStream_t s);
+
+// Bookkeeping after a chunk of k sweeps whose last two stored / reduced Phi.
+void commit_chunk(lkp_handle *h, int k);
+
+// Evaluate one check of the plain (F64 / F32) iteration.  prev_ok: the
+// reduced change compares consecutive sweeps.  Sets *converged; returns an
+// error status on divergence.
+lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
+                       const lkp_solve_opts &o, lkp_solve_report *rep, bool *converged);
+
+// F32_IR controller, split so that single and batched drivers share it.
+lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev);  // RESID sweep + finish
+lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lkp_solve_opts &o,
+                             lkp_solve_report *rep, bool *converged);
+SweepParams ir_inner_params(lkp_handle *h, int P);  // inner sweep d[dc] -> d[1-dc]
+lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
+                          const lkp_solve_opts &o, lkp_solve_report *rep);
+
+}  // namespace rt
+}  // namespace lkp

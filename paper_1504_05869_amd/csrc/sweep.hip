@@ -93,6 +93,22 @@ hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, 
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_sweep_batch(int lattice, int mode, int P, int flags, const void *bp, hipStream_t s) {
+  if (!sweep_variant_available(lattice, mode, P) || mode == MODE_RESID) return hipErrorInvalidValue;
+  switch (lattice) {
+    case D1Q5: return launch_batch_tu<D1Q5>(mode, P, flags, bp, s);
+    case D1Q9: return launch_batch_tu<D1Q9>(mode, P, flags, bp, s);
+    case D1Q13: return launch_batch_tu<D1Q13>(mode, P, flags, bp, s);
+    case D2Q5: return launch_batch_tu<D2Q5>(mode, P, flags, bp, s);
+    case D2Q9: return launch_batch_tu<D2Q9>(mode, P, flags, bp, s);
+    case D2Q25: return launch_batch_tu<D2Q25>(mode, P, flags, bp, s);
+    case D2Q81: return launch_batch_tu<D2Q81>(mode, P, flags, bp, s);
+    case D2Q169: return launch_batch_tu<D2Q169>(mode, P, flags, bp, s);
+    case D3Q111: return launch_batch_tu<D3Q111>(mode, P, flags, bp, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, out);
   return hipGetLastError();

@@ -3,4 +3,5 @@
 
 namespace lkp {
 template hipError_t launch_lattice_tu<D2Q5>(int, int, int, SweepParams, hipStream_t);
+template hipError_t launch_batch_tu<D2Q5>(int, int, int, const void *, hipStream_t);
 }  // namespace lkp

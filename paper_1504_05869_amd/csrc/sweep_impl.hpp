@@ -55,14 +55,66 @@ template <> struct ModeTraits<MODE_INNER> {
   static constexpr bool POPSRC = true, RESID = false;
 };
 
+// Cache policy of the streamed population planes: every value is read once
+// and written once per sweep, so the stores may skip cache allocation.
+#ifndef LKP_NT_STORE
+#define LKP_NT_STORE 1
+#endif
+#ifndef LKP_NT_LOAD
+#define LKP_NT_LOAD 0
+#endif
+#ifndef LKP_XCD_REMAP
+#define LKP_XCD_REMAP 1
+#endif
+
+template <typename T>
+__device__ __forceinline__ T ld(const char *base, unsigned byte_off) {
+  const T *p = reinterpret_cast<const T *>(base + byte_off);
+#if LKP_NT_LOAD
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+template <typename T>
+__device__ __forceinline__ void st(char *base, unsigned byte_off, T v) {
+  T *p = reinterpret_cast<T *>(base + byte_off);
+#if LKP_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 // Every product and sum of the collision rounds on its own (no fused
 // multiply-add), as the scheme is written: the kernel is bound by memory
 // traffic, so this costs nothing, and decisions taken on FP64 values (a stop
 // rule on max |dPhi|) see the same rounding as a plain evaluation.
 #pragma clang fp contract(off)
 
-template <int LID, int MODE, int P, int FLAGS>
-__global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
+// Coefficients of one problem: omega phi_i and chi_i in the compute precision.
+template <typename TC>
+struct CoefTable {  // precomputed on the host (single-problem launches)
+  const TC *c;
+  int q;
+  __device__ __forceinline__ TC wphi(int i) const { return c[i]; }
+  __device__ __forceinline__ TC chi(int i) const { return c[q + i]; }
+};
+
+template <typename TC>
+struct CoefScaled {  // batched launches: omega phi_i formed in FP64 exactly as the host does
+  double omega;
+  const double *phi;
+  const double *chi_;
+  __device__ __forceinline__ TC wphi(int i) const { return (TC)(omega * phi[i]); }
+  __device__ __forceinline__ TC chi(int i) const { return (TC)chi_[i]; }
+};
+
+// One block's share of a sweep: cells [blk * CELLS, blk * CELLS + CELLS) of
+// the problem described by p (SweepParams or BatchMember).
+template <int LID, int MODE, int P, int FLAGS, class Params, class C>
+__device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const C &coef) {
   using L = Lattice<LID>;
   using MT = ModeTraits<MODE>;
   using TIN = typename MT::TIN;
@@ -78,7 +130,6 @@ __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = wave % P;
   const int cw = wave / P;
-  const unsigned blk = xcd_remap(blockIdx.x, p.nblocks);
   const unsigned ci = (unsigned)(cw * 64 + lane);
   const unsigned c = blk * CELLS + ci;
   const bool valid = c < p.ncells;
@@ -94,11 +145,15 @@ __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
   static_for<0, 2 * VMY + 1>([&](auto J) { yw[J] = wrap_coord(y, (int)J - VMY, p.ny, simple); });
   static_for<0, 2 * VMZ + 1>([&](auto J) { zw[J] = wrap_coord(z, (int)J - VMZ, p.nz, simple); });
 
-  const size_t plane = p.ncells;
-  const TIN *__restrict__ fin = reinterpret_cast<const TIN *>(p.fin);
-  TOUT *__restrict__ fout = reinterpret_cast<TOUT *>(p.fout);
-  const TSRC *__restrict__ src = reinterpret_cast<const TSRC *>(p.src);
-  const TC *__restrict__ coef = reinterpret_cast<const TC *>(p.coef);
+  // Plane i starts at a wave-uniform base; lanes add a 32-bit byte offset
+  // (every plane is < 4 GiB), which maps to scalar-base + vector-offset
+  // addressing.
+  const size_t plane = p.plane;
+  const char *__restrict__ fin = reinterpret_cast<const char *>(p.fin);
+  char *__restrict__ fout = reinterpret_cast<char *>(p.fout);
+  const char *__restrict__ src = reinterpret_cast<const char *>(p.src);
+  const unsigned c_in = cc * (unsigned)sizeof(TIN);
+  const unsigned c_out = c * (unsigned)sizeof(TOUT);
 
   TIN vals[QG];
   double part = 0.0;
@@ -111,7 +166,7 @@ __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
       constexpr int i = decltype(I)::value;
       constexpr int vx = L::table.v[i][0], vy = L::table.v[i][1], vz = L::table.v[i][2];
       const unsigned off = (zw[vz + VMZ] * p.ny + yw[vy + VMY]) * p.nx + xw[vx + VMX];
-      vals[i - lo] = fin[(size_t)i * plane + off];
+      vals[i - lo] = ld<TIN>(fin + (size_t)i * plane * sizeof(TIN), off * (unsigned)sizeof(TIN));
     });
     // moment in velocity order, FP64
     static_for<lo, hi>([&](auto I) { part += (double)vals[(int)I - lo]; });
@@ -139,7 +194,7 @@ __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
   const TC phic = (TC)Phi;
   const TC om1 = (TC)p.om1;
   TC sc = 0;
-  if constexpr (!MT::POPSRC) sc = (TC)src[cc];
+  if constexpr (!MT::POPSRC) sc = (TC)ld<TSRC>(src, cc * (unsigned)sizeof(TSRC));
   double r2 = 0.0;
 
   auto store_group = [&](auto Gc) {
@@ -150,16 +205,19 @@ __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
       constexpr int i = decltype(I)::value;
       TC val;
       if constexpr (MT::POPSRC) {
-        val = om1 * (TC)vals[i - lo] + coef[i] * phic + (TC)src[(size_t)i * plane + cc];
+        const TSRC ri = ld<TSRC>(src + (size_t)i * plane * sizeof(TSRC), cc * (unsigned)sizeof(TSRC));
+        val = om1 * (TC)vals[i - lo] + coef.wphi(i) * phic + (TC)ri;
       } else {
-        val = om1 * (TC)vals[i - lo] + coef[i] * phic + coef[Q + i] * sc;
+        val = om1 * (TC)vals[i - lo] + coef.wphi(i) * phic + coef.chi(i) * sc;
       }
+      char *obase = fout + (size_t)i * plane * sizeof(TOUT);
       if constexpr (MT::RESID) {
-        const double r = (double)val - (double)fin[(size_t)i * plane + cc];
+        const double xi = (double)ld<TIN>(fin + (size_t)i * plane * sizeof(TIN), c_in);
+        const double r = (double)val - xi;
         r2 += r * r;
-        if (valid) fout[(size_t)i * plane + c] = (TOUT)r;
+        if (valid) st<TOUT>(obase, c_out, (TOUT)r);
       } else {
-        if (valid) fout[(size_t)i * plane + c] = (TOUT)val;
+        if (valid) st<TOUT>(obase, c_out, (TOUT)val);
       }
     });
   };
@@ -197,6 +255,43 @@ __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
   }
 }
 
+__device__ __forceinline__ unsigned block_order(unsigned b, unsigned nb) {
+#if LKP_XCD_REMAP
+  return xcd_remap(b, nb);
+#else
+  (void)nb;
+  return b;
+#endif
+}
+
+template <int LID, int MODE, int P, int FLAGS>
+__global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
+  using TC = typename ModeTraits<MODE>::TC;
+  const unsigned blk = block_order(blockIdx.x, p.nblocks);
+  CoefTable<TC> coef;
+  if constexpr (sizeof(TC) == 8) coef.c = p.coef.d;
+  else coef.c = p.coef.f;
+  coef.q = Lattice<LID>::Q;
+  sweep_block<LID, MODE, P, FLAGS>(p, blk, coef);
+}
+
+// Many problems of one lattice class in one launch: blocks are numbered
+// member after member; each block finds its member in the (wave-uniform)
+// table and sweeps its cells exactly as a single-problem launch would.
+template <int LID, int MODE, int P, int FLAGS>
+__global__ void __launch_bounds__(256) k_sweep_batch(BatchParams<Lattice<LID>::Q> bp) {
+  using TC = typename ModeTraits<MODE>::TC;
+  const unsigned gb = block_order(blockIdx.x, bp.nblocks);
+  unsigned j = 0;
+  for (unsigned k = 1; k < bp.nmembers; ++k)
+    if (bp.m[k].block_begin <= gb) j = k;
+  const BatchMember &m = bp.m[j];
+  CoefScaled<TC> coef{m.omega, bp.phi, bp.chi};
+  sweep_block<LID, MODE, P, FLAGS>(m, gb - m.block_begin, coef);
+}
+
+
+
 template <int LID, int MODE, int P>
 hipError_t launch_flags(int flags, SweepParams p, hipStream_t s) {
   dim3 grid(p.nblocks), block(256);
@@ -211,6 +306,49 @@ hipError_t launch_flags(int flags, SweepParams p, hipStream_t s) {
     return hipErrorInvalidValue;  // the residual sweep always reduces
   }
   return hipGetLastError();
+}
+
+template <int LID, int MODE, int P>
+hipError_t launch_batch_flags(int flags, const BatchParams<Lattice<LID>::Q> &bp, hipStream_t s) {
+  dim3 grid(bp.nblocks), block(256);
+  if constexpr (MODE == MODE_RESID) {
+    return hipErrorInvalidValue;  // residual sweeps are launched one problem at a time
+  } else {
+    if (flags & FLAG_REDUCE)
+      hipLaunchKernelGGL((k_sweep_batch<LID, MODE, P, FLAG_REDUCE | FLAG_PHI>), grid, block, 0, s, bp);
+    else if (flags & FLAG_PHI)
+      hipLaunchKernelGGL((k_sweep_batch<LID, MODE, P, FLAG_PHI>), grid, block, 0, s, bp);
+    else
+      hipLaunchKernelGGL((k_sweep_batch<LID, MODE, P, 0>), grid, block, 0, s, bp);
+  }
+  return hipGetLastError();
+}
+
+template <int LID, int MODE>
+hipError_t launch_batch_mode(int P, int flags, const void *bp, hipStream_t s) {
+  const auto &b = *reinterpret_cast<const BatchParams<Lattice<LID>::Q> *>(bp);
+  switch (P) {
+    case 1:
+      if constexpr (sweep_variant_built(LID, MODE, 1)) return launch_batch_flags<LID, MODE, 1>(flags, b, s);
+      break;
+    case 2:
+      if constexpr (sweep_variant_built(LID, MODE, 2)) return launch_batch_flags<LID, MODE, 2>(flags, b, s);
+      break;
+    case 4:
+      if constexpr (sweep_variant_built(LID, MODE, 4)) return launch_batch_flags<LID, MODE, 4>(flags, b, s);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int LID>
+hipError_t launch_batch_lattice(int mode, int P, int flags, const void *bp, hipStream_t s) {
+  switch (mode) {
+    case MODE_F64: return launch_batch_mode<LID, MODE_F64>(P, flags, bp, s);
+    case MODE_F32: return launch_batch_mode<LID, MODE_F32>(P, flags, bp, s);
+    case MODE_INNER: return launch_batch_mode<LID, MODE_INNER>(P, flags, bp, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int LID, int MODE>
@@ -245,6 +383,11 @@ hipError_t launch_lattice(int mode, int P, int flags, SweepParams p, hipStream_t
 template <int LID>
 hipError_t launch_lattice_tu(int mode, int P, int flags, SweepParams p, hipStream_t s) {
   return sweep_detail::launch_lattice<LID>(mode, P, flags, p, s);
+}
+
+template <int LID>
+hipError_t launch_batch_tu(int mode, int P, int flags, const void *bp, hipStream_t s) {
+  return sweep_detail::launch_batch_lattice<LID>(mode, P, flags, bp, s);
 }
 
 }  // namespace lkp

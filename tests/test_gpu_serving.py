@@ -1,0 +1,156 @@
+"""GPU tests of batched serving: alone vs in the mix, and the server end to end."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1504_05869_amd as lkp
+from paper_1504_05869_amd import serve
+from paper_1504_05869_amd import workloads as W
+from oracle import lattice as OL
+from oracle import spectral as SP
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-serving]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _source(shape, seed):
+    return W.zero_mean(W.gaussian_blobs(shape, 5, 1.5, seed))
+
+
+def _alone(spec, lattice, order, precision, K, tol):
+    shape, kn, seed = spec
+    with lkp.Problem(_source(shape, seed), lattice, order, knudsen=kn, precision=precision) as p:
+        rep = p.solve(tol_rel_l2=tol, check_every=K, max_sweeps=500000)
+        return p.phi_host(), rep["sweeps"]
+
+
+def _mix(specs, lattice, order, precision, K, tol, join_at):
+    g = lkp.Group(lattice, order, precision)
+    probs, out, tick = {}, {}, 0
+    pending = list(range(len(specs)))
+    try:
+        while pending or len(g):
+            for k in list(pending):
+                if join_at[k] <= tick:
+                    shape, kn, seed = specs[k]
+                    p = lkp.Problem(_source(shape, seed), lattice, order, knudsen=kn,
+                                    precision=precision)
+                    g.add(p, tol_rel_l2=tol, max_sweeps=500000)
+                    probs[p._h.value] = (k, p)
+                    pending.remove(k)
+            if len(g):
+                for r in g.step(K):
+                    if r["state"] == "running":
+                        continue
+                    assert r["state"] == "converged", r
+                    k, p = probs[r["problem"]._h.value]
+                    out[k] = (p.phi_host(), r["sweeps"])
+                    g.remove(p)
+                    p.close()
+            tick += 1
+            assert tick < 100000
+    finally:
+        g.close()
+    return out
+
+
+CASES = [
+    ("D2Q81", 5, "f64", 2, [((48, 40), 0.1, 1), ((33, 65), 0.3, 2), ((64, 64), 0.05, 3),
+                            ((17, 23), 0.2, 4)]),
+    ("D2Q81", 5, "f32_ir", None, [((48, 40), 0.1, 1), ((33, 65), 0.3, 2), ((64, 64), 0.05, 3)]),
+    ("D3Q111", 5, "f32_ir", None, [((12, 10, 16), 0.2, 5), ((9, 11, 13), 0.1, 6),
+                                   ((16, 16, 16), 0.4, 7)]),
+    ("D2Q169", 7, "f64", 4, [((30, 36), 0.1, 8), ((21, 25), 0.3, 9)]),
+]
+
+
+@pytest.mark.parametrize("lattice,order,precision,split,specs", CASES)
+def test_alone_equals_mix_bitwise(lattice, order, precision, split, specs):
+    """Each problem's answer and sweep count are identical solved alone
+    (lkp_solve) and inside a batched group whose membership changes."""
+    K = 20
+    tol = 1e-9 if precision == "f64" else 1e-8
+    if split:
+        os.environ["LKP_SPLIT"] = str(split)
+    try:
+        alone = [_alone(s, lattice, order, precision, K, tol) for s in specs]
+        join_at = [0, 0] + [3 + 2 * k for k in range(len(specs) - 2)]
+        mix = _mix(specs, lattice, order, precision, K, tol, join_at)
+    finally:
+        os.environ.pop("LKP_SPLIT", None)
+    for k, (phi, sweeps) in enumerate(alone):
+        say(lattice, precision, specs[k][0], "alone sweeps", sweeps, "mix sweeps", mix[k][1])
+        assert mix[k][1] == sweeps
+        assert np.array_equal(mix[k][0], phi)
+    # and the answers are the scheme's fixed point
+    for k, (shape, kn, seed) in enumerate(specs):
+        tau = OL.tau_from_knudsen(kn, OL.get(lattice), min(shape))
+        ref = SP.fixed_point(lattice, order, tau, _source(shape, seed))
+        err = rel_l2(alone[k][0], ref)
+        say("true error", shape, err)
+        assert err <= (1e-8 if precision == "f64" else 2e-7)
+
+
+def test_group_rejects_other_class_and_stream():
+    s = _source((16, 16), 1)
+    g = lkp.Group("D2Q81", 5, "f64")
+    with lkp.Problem(s, "D2Q25", 3, tau_lb=2.0) as p:
+        with pytest.raises(lkp.LkpError):
+            g.add(p, tol_rel_l2=1e-8)
+    with lkp.Problem(s, "D2Q81", 5, tau_lb=2.0, precision="f32") as p:
+        with pytest.raises(lkp.LkpError):
+            g.add(p, tol_rel_l2=1e-8)
+    with lkp.Problem(s, "D2Q81", 5, tau_lb=2.0) as p:
+        g.add(p, tol_rel_l2=1e-8)
+        with pytest.raises(lkp.LkpError):
+            p.solve(tol_rel_l2=1e-8)          # resident in a group
+        with pytest.raises(lkp.LkpError):
+            g.add(p, tol_rel_l2=1e-8)         # already a member
+    assert len(g._members) in (0, 1)
+    g.close()
+
+
+def test_group_member_limit_reported():
+    s = _source((24, 24), 2)
+    g = lkp.Group("D2Q25", 3, "f64")
+    with lkp.Problem(s, "D2Q25", 3, tau_lb=1.0) as p:
+        g.add(p, tol_rel_l2=1e-14, max_sweeps=40)
+        reps = []
+        for _ in range(5):
+            reps = g.step(20)
+        assert reps[0]["state"] == "failed" and reps[0]["status"] == "LKP_ERR_NOT_CONVERGED"
+        assert reps[0]["sweeps"] == 40
+    g.close()
+
+
+def test_server_end_to_end_small_stream():
+    """A small mixed 2D/3D stream through the continuous-batching server, with
+    the one-at-a-time FP64 baseline on the same trace; answers agree and meet
+    the tolerance against the exact fixed point."""
+    reqs = serve.make_stream(10, rate=400.0, seed=11, sizes2d=((32, 32), (48, 64), (64, 64)),
+                             sizes3d=((12, 12, 12), (16, 16, 16)))
+    srv = serve.Server(serve.GpuBackend("f32_ir", keep_phi=True), hbm_budget=2 << 30,
+                       sweeps_per_tick=20, tol=1e-7)
+    res, summ = srv.run(reqs)
+    say("served", summ)
+    base, bsum = serve.run_one_at_a_time(reqs, "f64", tol=1e-7, check_every=20, keep_phi=True)
+    say("one at a time", bsum)
+    assert summ["completed"] == len(reqs) and bsum["completed"] == len(reqs)
+    for r, b, q in zip(res, base, sorted(reqs, key=lambda x: x.arrival)):
+        s = W.poisson_source(q.kind, q.shape, seed=q.seed)
+        tau = OL.tau_from_knudsen(q.knudsen, OL.get(q.lattice), min(q.shape))
+        ref = SP.fixed_point(q.lattice, q.order, tau, s)
+        e_srv, e_base = rel_l2(r.phi, ref), rel_l2(b.phi, ref)
+        say(q.shape, q.knudsen, "served err", e_srv, "baseline err", e_base)
+        assert e_srv <= 1e-6 and e_base <= 1e-6
+    assert summ["peak_hbm_bytes"] <= 2 << 30
