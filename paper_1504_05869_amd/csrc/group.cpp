@@ -55,7 +55,7 @@ struct Slot {
 };
 
 template <int Q>
-lkp_status launch_slots(lkp_group *g, int flags, const std::vector<Slot> &slots) {
+lkp_status launch_slots(lkp_group *g, int mode, int flags, const std::vector<Slot> &slots) {
   constexpr int cap = batch_capacity(Q);
   BatchParams<Q> bp;
   std::memset(&bp, 0, sizeof bp);
@@ -90,22 +90,22 @@ lkp_status launch_slots(lkp_group *g, int flags, const std::vector<Slot> &slots)
       m.block_begin = bp.nblocks;
       bp.nblocks += m.nblocks;
     }
-    hipError_t err = launch_sweep_batch(g->lattice, g->mode(), g->P, flags, &bp, g->stream);
+    hipError_t err = launch_sweep_batch(g->lattice, mode, g->P, flags, &bp, g->stream);
     if (err != hipSuccess) return fail(LKP_ERR_HIP, "batched sweep launch: %s", hipGetErrorString(err));
   }
   return LKP_OK;
 }
 
-lkp_status launch_batched(lkp_group *g, int flags, const std::vector<Slot> &slots) {
+lkp_status launch_batched(lkp_group *g, int mode, int flags, const std::vector<Slot> &slots) {
   if (slots.empty()) return LKP_OK;
   switch (g->Q) {
-    case 5: return launch_slots<5>(g, flags, slots);
-    case 9: return launch_slots<9>(g, flags, slots);
-    case 13: return launch_slots<13>(g, flags, slots);
-    case 25: return launch_slots<25>(g, flags, slots);
-    case 81: return launch_slots<81>(g, flags, slots);
-    case 111: return launch_slots<111>(g, flags, slots);
-    case 169: return launch_slots<169>(g, flags, slots);
+    case 5: return launch_slots<5>(g, mode, flags, slots);
+    case 9: return launch_slots<9>(g, mode, flags, slots);
+    case 13: return launch_slots<13>(g, mode, flags, slots);
+    case 25: return launch_slots<25>(g, mode, flags, slots);
+    case 81: return launch_slots<81>(g, mode, flags, slots);
+    case 111: return launch_slots<111>(g, mode, flags, slots);
+    case 169: return launch_slots<169>(g, mode, flags, slots);
   }
   return fail(LKP_ERR_UNSUPPORTED, "no batched sweep for Q = %d", g->Q);
 }
@@ -143,7 +143,7 @@ lkp_status step_plain(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
       s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
       cur[k] = 1 - cur[k];
     }
-    if (lkp_status st = launch_batched(g, flags, slots)) return st;
+    if (lkp_status st = launch_batched(g, g->mode(), flags, slots)) return st;
   }
   for (size_t k = 0; k < run.size(); ++k)
     if (lkp_status st = finish_norms(run[k], sweep_blocks(run[k], g->P),
@@ -171,6 +171,9 @@ lkp_status step_plain(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
 // One refinement step round: residuals for members that need one, then K
 // batched inner sweeps for members inside an inner solve.
 lkp_status step_ir(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
+  for (lkp_handle *h : run)
+    if (h->ir.phase == IR_START)
+      if (lkp_status st = ir_begin_inner(h, h->gopts)) return st;
   std::vector<lkp_handle *> res;
   for (lkp_handle *h : run)
     if (h->ir.phase == IR_RESID) res.push_back(h);
@@ -194,23 +197,30 @@ lkp_status step_ir(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
     }
     inner.push_back(h);
   }
-  std::vector<Slot> slots(inner.size());
+  // first solves run the plain FP32 sweep, corrections the residual-source
+  // sweep: one batched launch per kind
+  std::vector<Slot> first, corr;
   for (int j = 0; j < K; ++j) {
     int flags = 0;
     if (j == K - 2) flags = FLAG_PHI;
     if (j == K - 1) flags = FLAG_REDUCE;
+    first.clear();
+    corr.clear();
     for (size_t k = 0; k < inner.size(); ++k) {
       lkp_handle *h = inner[k];
-      Slot &s = slots[k];
+      Slot s;
       s.h = h;
       s.fin = h->d32[h->ir.dc];
       s.fout = h->d32[1 - h->ir.dc];
-      s.src = h->r32;
+      const bool plain = ir_inner_mode(h) == MODE_F32;
+      s.src = plain ? (const void *)h->S32 : (const void *)h->r32;
       s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
       s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
       h->ir.dc = 1 - h->ir.dc;
+      (plain ? first : corr).push_back(s);
     }
-    if (lkp_status st = launch_batched(g, flags, slots)) return st;
+    if (lkp_status st = launch_batched(g, MODE_F32, flags, first)) return st;
+    if (lkp_status st = launch_batched(g, MODE_INNER, flags, corr)) return st;
   }
   for (size_t k = 0; k < inner.size(); ++k)
     if (lkp_status st = finish_norms(inner[k], sweep_blocks(inner[k], g->P),

@@ -178,6 +178,29 @@ lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
   return finish_norms(h, sweep_blocks(h, P), dst_dev, h->stream);
 }
 
+lkp_status ir_begin_inner(lkp_handle *h, const lkp_solve_opts &o) {
+  IrState &s = h->ir;
+  if (s.phase == IR_START) s.rnorm = h->g_norm;  // residual of x = 0
+  const size_t QN = (size_t)h->Q * h->ncells;
+  LKP_HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
+  s.dc = 0;
+  // Inner accuracy: as asked, or just enough to close the remaining gap
+  // (30 % margin), never below the FP32 sweep's own floor (~1e-7 relative).
+  if (o.ir_inner_tol > 0) {
+    s.inner_tol = o.ir_inner_tol;
+  } else {
+    const double want = s.est > 0 ? 0.3 * o.tol_rel_l2 / s.est : 1e-1;
+    s.inner_tol = std::min(1e-1, std::max(1e-7, want));
+  }
+  s.l2_prev = -1;
+  s.best_l2 = 1e300;
+  s.stall = 0;
+  s.t_in = 0;
+  s.t_prev = 0;
+  s.phase = IR_INNER;
+  return LKP_OK;
+}
+
 lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lkp_solve_opts &o,
                              lkp_solve_report *rep, bool *converged) {
   IrState &s = h->ir;
@@ -204,33 +227,18 @@ lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lk
   }
   const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
   if (s.outer >= max_outer) return fail(LKP_ERR_NOT_CONVERGED, "refinement: %d outer steps", s.outer);
-  // start the inner solve from d = 0
-  const size_t QN = (size_t)h->Q * h->ncells;
-  LKP_HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
-  s.dc = 0;
-  // Inner accuracy: as asked, or just enough to close the remaining gap
-  // (30 % margin), never below the FP32 sweep's own floor (~1e-7 relative).
-  if (o.ir_inner_tol > 0) {
-    s.inner_tol = o.ir_inner_tol;
-  } else {
-    const double want = s.est > 0 ? 0.3 * o.tol_rel_l2 / s.est : 1e-1;
-    s.inner_tol = std::min(1e-1, std::max(1e-7, want));
-  }
-  s.l2_prev = -1;
-  s.best_l2 = 1e300;
-  s.stall = 0;
-  s.t_in = 0;
-  s.t_prev = 0;
-  s.phase = IR_INNER;
-  return LKP_OK;
+  return ir_begin_inner(h, o);
 }
+
+int ir_inner_mode(const lkp_handle *h) { return h->ir.outer == 0 ? MODE_F32 : MODE_INNER; }
 
 SweepParams ir_inner_params(lkp_handle *h, int P) {
   SweepParams p = base_params(h);
+  const int mode = ir_inner_mode(h);
   p.fin = h->d32[h->ir.dc];
   p.fout = h->d32[1 - h->ir.dc];
-  p.src = h->r32;
-  set_coefficients(h, MODE_INNER, &p);
+  p.src = mode == MODE_F32 ? (const void *)h->S32 : (const void *)h->r32;
+  set_coefficients(h, mode, &p);
   p.partials = h->partials;
   (void)P;
   return p;
@@ -247,13 +255,22 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
     const double r = std::pow(l2 / s.l2_prev, 1.0 / (double)(s.t_in - s.t_prev));
     if (r < 1) s.rate = r;
   }
-  s.stall = (l2 < 0.95 * s.best_l2) ? 0 : s.stall + 1;
+  // Stagnation at the FP32 rounding floor: the change stops shrinking at
+  // (half) the contraction rate measured while it still converged.
+  const bool no_progress =
+      s.l2_prev > 0 && (s.rate > 0 ? l2 >= s.l2_prev * std::pow(s.rate, 0.5 * K) : l2 >= s.l2_prev);
+  s.stall = (no_progress && s.t_in >= 4 * (int64_t)K) ? s.stall + 1 : 0;
   s.best_l2 = std::min(s.best_l2, l2);
   s.l2_prev = l2;
   s.t_prev = s.t_in;
   rep->rate = s.rate;
   const double est = (s.rate > 0 && s.rate < 1) ? l2 * s.rate / (1 - s.rate) : 1e300;
-  if (!(s.corr == 0 || est <= s.inner_tol * s.corr || s.stall >= 3)) return LKP_OK;
+  // FP32 sweeps cannot bring the correction closer than about u32 / (1 - rho)
+  // of its size (rounding of each sweep, amplified by the slow contraction);
+  // stop there rather than sweep on without gaining accuracy.
+  const double floor32 = (s.rate > 0 && s.rate < 1) ? 2.0 * 5.96e-8 / (1 - s.rate) : 0.0;
+  const double goal = std::max(s.inner_tol, floor32);
+  if (!(s.corr == 0 || est <= goal * s.corr || s.stall >= 2)) return LKP_OK;
   // inner solve done: x += d - phi_i mean(d), FP64
   const size_t QN = (size_t)h->Q * h->ncells;
   unsigned nb = 0;
@@ -351,7 +368,7 @@ int64_t footprint_of(int precision, int Q, int64_t ncells) {
   int64_t b = 3 * 8 * ncells + nb * NUM_NORMS * 8 + 4096;  // S + 2 Phi + partials + misc
   if (precision == LKP_F64) b += 2 * 8 * (int64_t)Q * ncells;
   else if (precision == LKP_F32) b += 2 * 4 * (int64_t)Q * ncells;
-  else b += 8 * (int64_t)Q * ncells + 3 * 4 * (int64_t)Q * ncells;  // x + r + 2 d
+  else b += 8 * (int64_t)Q * ncells + 3 * 4 * (int64_t)Q * ncells + 4 * ncells;  // x, r, 2 d, S32
   return b;
 }
 
@@ -513,7 +530,7 @@ lkp_status upload_coefficients(lkp_handle *h) {
 
 void release(lkp_handle *h) {
   drop_graphs(h);
-  void *ptrs[] = {h->f[0], h->f[1], h->S, h->phi_dev, h->r32, h->d32[0],
+  void *ptrs[] = {h->f[0], h->f[1], h->S, h->S32, h->phi_dev, h->r32, h->d32[0],
                   h->d32[1], h->phib[0], h->phib[1], h->partials, h->norms_dev};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -599,6 +616,16 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
     HIP_TRY(hipMalloc(&h->d32[1], Q * n * 4));
     HIP_TRY(hipMalloc(&h->S, n * 8));
     HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
+    std::vector<float> S32(n);
+    long double s2 = 0, c2 = 0;
+    for (size_t c = 0; c < n; ++c) {
+      S32[c] = (float)S[c];
+      s2 += (long double)S[c] * S[c];
+    }
+    for (int i = 0; i < h->Q; ++i) c2 += (long double)h->chi[i] * h->chi[i];
+    h->g_norm = (double)std::sqrt(s2 * c2);
+    HIP_TRY(hipMalloc(&h->S32, n * 4));
+    HIP_TRY(hipMemcpy(h->S32, S32.data(), n * 4, hipMemcpyHostToDevice));
   }
   HIP_TRY(hipMalloc(&h->phib[0], n * 8));
   HIP_TRY(hipMalloc(&h->phib[1], n * 8));
@@ -711,6 +738,8 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
     bool converged = false;
     while (!converged) {
       double nr[NUM_NORMS];
+      if (h->ir.phase == IR_START)
+        if (lkp_status st = ir_begin_inner(h, *o)) return st;
       if (h->ir.phase == IR_RESID) {
         if (lkp_status st = ir_launch_residual(h, h->norms_dev)) return st;
         if (lkp_status st = read_back(h, nr)) return st;
@@ -728,7 +757,7 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
         int flags = 0;
         if (j == K - 2) { flags = FLAG_PHI; p.phi_out = h->phib[0]; }
         if (j == K - 1) { flags = FLAG_REDUCE; p.phi_prev = h->phib[0]; p.phi_out = h->phib[1]; }
-        hipError_t e = launch_sweep(h->lattice, MODE_INNER, P, flags, p, h->stream);
+        hipError_t e = launch_sweep(h->lattice, ir_inner_mode(h), P, flags, p, h->stream);
         if (e != hipSuccess) return fail(LKP_ERR_HIP, "inner sweep launch: %s", hipGetErrorString(e));
         h->ir.dc = 1 - h->ir.dc;
       }

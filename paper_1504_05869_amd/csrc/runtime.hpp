@@ -40,9 +40,12 @@ struct Tracker {
 };
 
 // Iterative-refinement controller state of one F32_IR problem.
-enum IrPhase : int { IR_RESID = 0, IR_INNER = 1, IR_DONE = 2 };
+// IR_START: the first solve (from x = 0) has the plain source chi_i S, so it
+// runs the plain FP32 sweep; later corrections solve with the population
+// residual r as source (MODE_INNER).
+enum IrPhase : int { IR_START = 0, IR_RESID = 1, IR_INNER = 2, IR_DONE = 3 };
 struct IrState {
-  int phase = IR_RESID;
+  int phase = IR_START;
   int outer = 0;
   double rnorm = -1.0, rnorm_prev = -1.0;
   double corr = 0.0, corr_prev = -1.0;
@@ -74,6 +77,8 @@ struct lkp_handle {
   void *f[2] = {nullptr, nullptr};
   int cur = 0;
   void *S = nullptr;          // scaled source in the sweep precision (double for IR)
+  float *S32 = nullptr;       // IR: the scaled source rounded to FP32 (first solve)
+  double g_norm = 0.0;        // IR: ||chi_i S||_2, the residual of x = 0
   double *phi_dev = nullptr;  // phi_i on the device (IR mass projection)
   float *r32 = nullptr;
   float *d32[2] = {nullptr, nullptr};
@@ -128,6 +133,8 @@ lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
 lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev);  // RESID sweep + finish
 lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lkp_solve_opts &o,
                              lkp_solve_report *rep, bool *converged);
+lkp_status ir_begin_inner(lkp_handle *h, const lkp_solve_opts &o);  // d = 0, tolerance
+int ir_inner_mode(const lkp_handle *h);             // MODE_F32 (first solve) or MODE_INNER
 SweepParams ir_inner_params(lkp_handle *h, int P);  // inner sweep d[dc] -> d[1-dc]
 lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
                           const lkp_solve_opts &o, lkp_solve_report *rep);
