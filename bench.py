@@ -39,9 +39,10 @@ def bytes_per_cell(Q: int, precision: str) -> int:
 
 
 def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=None,
-               sweeps=200, chunks=1):
+               sweeps=200, chunks=1, population_sweep=False):
     """Average duration of one sweep (HIP events on the solver's stream)."""
-    with lkp.Problem(s, lattice, order, knudsen=knudsen, tau_lb=tau_lb, precision=precision) as p:
+    with lkp.Problem(s, lattice, order, knudsen=knudsen, tau_lb=tau_lb, precision=precision,
+                     population_sweep=population_sweep) as p:
         p.step(2)
         p.sync()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -58,7 +59,8 @@ def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=No
             "ms_per_sweep": ms, "glups": n / (ms * 1e-3) / 1e9,
             "gbs": n * bpc / (ms * 1e-3) / 1e9,
             "frac_hbm": n * bpc / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "velocity_groups": info["velocity_groups"], "tau_lb": info["tau_lb"]}
+            "velocity_groups": info["velocity_groups"], "tau_lb": info["tau_lb"],
+            "form": "stencil (tau_lb=1)" if info["scalar_stencil"] else "population sweep"}
 
 
 KERNEL_SOURCES = ["paper_1504_05869_amd/csrc/sweep_impl.hpp", "paper_1504_05869_amd/csrc/lattices.hpp",
@@ -231,10 +233,31 @@ def main():
         s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
         for prec in ("f32", "f64"):
             extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
-                                          sweeps=40), grid="256^3"))
-        del s3
+                                          sweeps=40, population_sweep=True), grid="256^3"))
+        # tau_lb = 1: the stencil form (state Phi, 3 values moved per cell)
+        for prec in ("f32", "f64"):
+            r = sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0, sweeps=200)
+            b = 4 if prec == "f32" else 8
+            r.update(form="stencil (tau_lb=1)", grid="256^3",
+                     gbs=s3.size * 3 * b / (r["ms_per_sweep"] * 1e-3) / 1e9)
+            r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
+            extras.append(r)
         out["sweeps"] = [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in e.items()}
                          for e in extras]
+        # 256^3 D3Q111 N=5 at tau_lb = 1 (512 Gaussians + sine background):
+        # time to rel-L2 1e-6 in FP32 + refinement and in FP64, stencil form
+        tts3 = []
+        for prec in ("f32_ir", "f64"):
+            with lkp.Problem(s3, "D3Q111", 5, tau_lb=1.0, precision=prec) as q:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                rep = q.solve(tol_rel_l2=1e-6, check_every=200, max_sweeps=2_000_000)
+                torch.cuda.synchronize()
+                tts3.append({"precision": prec, "tol_rel_l2": 1e-6, "form": "stencil (tau_lb=1)",
+                             "seconds": round(time.perf_counter() - t1, 4), "sweeps": rep["sweeps"],
+                             "outer": rep["outer"], "est_rel_err": rep["est_rel_err"]})
+        out["time_to_solution_256cubed"] = tts3
+        del s3
         # time-to-solution on the headline problem, FP64 and FP32 + refinement
         tts = []
         for prec, tol in (("f64", 1e-10), ("f32_ir", 1e-10), ("f32_ir", 1e-6)):

@@ -75,6 +75,14 @@ typedef enum lkp_precision {
   LKP_F32_IR = 2  /* FP32 inner sweeps inside FP64 iterative refinement on the population state */
 } lkp_precision;
 
+/* At tau_lb = 1 (omega = 1) the collision forgets the populations: after a
+ * sweep f*_i = phi_i Phi + chi_i S, so the next moment is the scalar stencil
+ * Phi' = sum_i phi_i Phi(x - v_i) + sum_i chi_i S(x - v_i).  Handles then keep
+ * Phi alone and sweep with that stencil (same answer, same sweep count, far
+ * fewer bytes); populations are rebuilt on request and cannot be set.  This
+ * flag keeps the population sweep instead. */
+#define LKP_FLAG_POPULATION_SWEEP 1
+
 typedef struct lkp_problem_desc {
   int32_t dim;              /* 1, 2 or 3; must equal the lattice's dimension */
   int32_t lattice;          /* lkp_lattice */
@@ -91,7 +99,7 @@ typedef struct lkp_problem_desc {
   int32_t source_on_device; /* 1: `source` is a device pointer */
   int32_t subtract_mean;    /* 1: remove the mean of s instead of rejecting it */
   int32_t allow_unstable;   /* 1: skip the tau_lb stability check */
-  int32_t reserved;
+  int32_t flags;            /* LKP_FLAG_* bits */
   void *stream;             /* hipStream_t for all of this handle's work; NULL = default */
 } lkp_problem_desc;
 
@@ -184,6 +192,8 @@ lkp_status lkp_lattice_info(int32_t lattice, int32_t order, int32_t *Q, int32_t 
 
 typedef struct lkp_handle_info {
   int32_t lattice, order, dim, Q, precision, velocity_groups;
+  int32_t scalar_stencil;   /* 1: omega = 1 stencil form (state is Phi) */
+  int32_t reserved;
   int64_t n[3];
   double tau_lb, omega, cs2;
   int64_t total_sweeps;

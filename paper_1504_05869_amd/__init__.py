@@ -96,7 +96,7 @@ class Problem:
 
     def __init__(self, source, lattice: str, order: int, tau_lb=None, knudsen=None,
                  precision: str = "f64", subtract_mean: bool = False,
-                 allow_unstable: bool = False, stream=None):
+                 allow_unstable: bool = False, stream=None, population_sweep: bool = False):
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         if isinstance(source, torch.Tensor):
@@ -114,6 +114,7 @@ class Problem:
                   allow_unstable)
         d.source = ptr
         d.source_on_device = int(on_dev)
+        d.flags = _lib.FLAG_POPULATION_SWEEP if population_sweep else 0
         self._stream = _stream_handle(stream)
         d.stream = self._stream
         self.lattice, self.order, self.precision = lattice, int(order), precision

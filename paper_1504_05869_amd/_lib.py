@@ -23,6 +23,7 @@ EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_solve", "lkp
            "lkp_group_create", "lkp_group_add", "lkp_group_remove", "lkp_group_step",
            "lkp_group_destroy"]
 MEMBER_STATES = {0: "running", 1: "converged", 2: "failed"}
+FLAG_POPULATION_SWEEP = 1
 
 
 class ProblemDesc(ctypes.Structure):
@@ -31,7 +32,7 @@ class ProblemDesc(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("tau_lb", ctypes.c_double),
                 ("knudsen", ctypes.c_double), ("source", ctypes.c_void_p),
                 ("source_on_device", ctypes.c_int32), ("subtract_mean", ctypes.c_int32),
-                ("allow_unstable", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("allow_unstable", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -60,7 +61,8 @@ class ResidualReport(ctypes.Structure):
 class HandleInfo(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("order", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("Q", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("velocity_groups", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("velocity_groups", ctypes.c_int32), ("scalar_stencil", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
                 ("tau_lb", ctypes.c_double), ("omega", ctypes.c_double),
                 ("cs2", ctypes.c_double), ("total_sweeps", ctypes.c_int64),
                 ("footprint_bytes", ctypes.c_int64)]

@@ -271,6 +271,8 @@ lkp_status lkp_group_add(lkp_group *g, lkp_handle *h, const lkp_solve_opts *o) {
   if (h->lattice != g->lattice || h->order != g->order || h->precision != g->precision)
     return fail(LKP_ERR_ARG, "handle class (lattice, order, precision) differs from the group's");
   if (h->stream != g->stream) return fail(LKP_ERR_ARG, "handle stream differs from the group's");
+  if (h->scalar)
+    return fail(LKP_ERR_UNSUPPORTED, "tau_lb = 1 stencil-form handles are solved with lkp_solve");
   if (!(o->tol_rel_l2 > 0) && !(o->tol_maxchange > 0))
     return fail(LKP_ERR_ARG, "give tol_rel_l2 or tol_maxchange");
   if (h->precision == LKP_F32_IR && !(o->tol_rel_l2 > 0))

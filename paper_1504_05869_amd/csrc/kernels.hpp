@@ -92,6 +92,36 @@ static_assert(sizeof(BatchParams<169>) <= 4096, "batched launch arguments exceed
 static_assert(sizeof(BatchParams<111>) <= 4096, "batched launch arguments exceed 4 KiB");
 static_assert(sizeof(BatchParams<5>) <= 4096, "batched launch arguments exceed 4 KiB");
 
+// ---- omega = 1: the sweep as a scalar stencil on Phi --------------------
+enum StencilMode : int {
+  SMODE_F64 = 0,   // FP64 in/out, FP64 source field
+  SMODE_F32 = 1,   // FP32 in/out, FP32 source field
+  SMODE_RESID = 2  // FP64 in, FP32 out R = A X + G - X (FP64 arithmetic)
+};
+
+struct StencilParams {
+  const void *xin;   // Phi (n values)
+  void *xout;        // next Phi (or R in SMODE_RESID)
+  const void *src;   // additive field (G, or R for correction solves); may be null
+  double *partials;  // NUM_NORMS per block (FLAG_REDUCE)
+  unsigned nx, ny, nz;
+  unsigned simple_wrap;
+  union {            // stencil weights per velocity (phi_i, or chi_i to form G)
+    double d[MAXQ];
+    float f[MAXQ];
+  } coef;
+};
+
+template <int LID>
+hipError_t launch_stencil_tu(int smode, int flags, const StencilParams &p, hipStream_t s);
+
+// One stencil sweep Phi' = sum_i c_i Phi(x - v_i) [+ src]; FLAG_REDUCE adds
+// the block norms of Phi' - Phi (or of R).
+hipError_t launch_stencil(int lattice, int smode, int flags, const StencilParams &p, hipStream_t s);
+
+// Blocks of a stencil launch on an nx x ny x nz grid.
+unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz);
+
 // Cells one block covers for a velocity-group split P (256 threads = 4 waves;
 // P waves share one 64-cell column and each holds Q/P populations).
 inline unsigned cells_per_block(int P) { return 256u / (unsigned)P; }

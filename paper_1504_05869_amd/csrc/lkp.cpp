@@ -161,6 +161,22 @@ lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
 // phi_i of T with eigenvalue 1) at the zero of the initial state.
 
 lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
+  if (h->scalar) {  // R = A x + G - x on the Phi state
+    StencilParams p{};
+    p.nx = (unsigned)h->n[0];
+    p.ny = (unsigned)h->n[1];
+    p.nz = (unsigned)h->n[2];
+    p.simple_wrap = h->simple_wrap ? 1u : 0u;
+    p.partials = h->partials;
+    for (int i = 0; i < h->Q; ++i) p.coef.d[i] = h->phi[i];
+    p.xin = h->f[0];
+    p.xout = h->r32;
+    p.src = h->S;
+    hipError_t e = launch_stencil(h->lattice, SMODE_RESID, FLAG_REDUCE, p, h->stream);
+    if (e != hipSuccess) return fail(LKP_ERR_HIP, "residual stencil launch: %s", hipGetErrorString(e));
+    h->total_sweeps += 1;
+    return finish_norms(h, stencil_blocks(h->lattice, p.nx, p.ny, p.nz), dst_dev, h->stream);
+  }
   const int P = default_split(h->Q, MODE_RESID);
   SweepParams p = base_params(h);
   p.fin = h->f[0];
@@ -181,7 +197,7 @@ lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
 lkp_status ir_begin_inner(lkp_handle *h, const lkp_solve_opts &o) {
   IrState &s = h->ir;
   if (s.phase == IR_START) s.rnorm = h->g_norm;  // residual of x = 0
-  const size_t QN = (size_t)h->Q * h->ncells;
+  const size_t QN = (size_t)(h->scalar ? 1 : h->Q) * h->ncells;
   LKP_HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
   s.dc = 0;
   // Inner accuracy: as asked, or just enough to close the remaining gap
@@ -271,12 +287,13 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
   const double floor32 = (s.rate > 0 && s.rate < 1) ? 2.0 * 5.96e-8 / (1 - s.rate) : 0.0;
   const double goal = std::max(s.inner_tol, floor32);
   if (!(s.corr == 0 || est <= goal * s.corr || s.stall >= 2)) return LKP_OK;
-  // inner solve done: x += d - phi_i mean(d), FP64
-  const size_t QN = (size_t)h->Q * h->ncells;
+  // inner solve done: x += d - phi_i mean(d), FP64 (scalar state: x += d - mean(d))
+  const int q = h->scalar ? 1 : h->Q;
+  const size_t QN = (size_t)q * h->ncells;
   unsigned nb = 0;
   LKP_HIP_TRY(launch_sum_f32(h->d32[s.dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream));
   LKP_HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
-  LKP_HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[s.dc], h->phi_dev, h->norms_dev, h->Q,
+  LKP_HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[s.dc], h->phi_dev, h->norms_dev, q,
                                h->ncells, h->stream));
   s.outer += 1;
   s.corr_prev = s.corr;
@@ -454,10 +471,44 @@ lkp_status read_norms(lkp_handle *h, unsigned nblocks, double out[NUM_NORMS]) {
   return LKP_OK;
 }
 
+StencilParams stencil_params(const lkp_handle *h);
+void stencil_weights(const lkp_handle *h, bool fp32, StencilParams *p);
+
+// One omega = 1 sweep number t (1-based) of the Phi state: sweep 1 starts
+// from f* = 0, so its Phi is exactly 0; later sweeps apply the stencil.
+lkp_status scalar_sweep(lkp_handle *h, hipStream_t s, int64_t t, int in, int out, int flags) {
+  const size_t n = h->ncells;
+  const bool fp32 = h->precision == LKP_F32;
+  if (t == 1) {
+    if (fp32) HIP_TRY(launch_fill_f32((float *)h->f[out], 0.0f, n, s));
+    else HIP_TRY(launch_fill_f64((double *)h->f[out], 0.0, n, s));
+    return LKP_OK;
+  }
+  StencilParams p = stencil_params(h);
+  stencil_weights(h, fp32, &p);
+  p.xin = h->f[in];
+  p.xout = h->f[out];
+  p.src = h->S;
+  HIP_TRY(launch_stencil(h->lattice, fp32 ? SMODE_F32 : SMODE_F64, flags, p, s));
+  return LKP_OK;
+}
+
+unsigned scalar_blocks(const lkp_handle *h) {
+  return stencil_blocks(h->lattice, (unsigned)h->n[0], (unsigned)h->n[1], (unsigned)h->n[2]);
+}
+
 // Enqueue a chunk of k >= 1 sweeps whose last sweep reduces norms (and, for
 // k >= 2, compares with the sweep before it).  Updates cur / phi bookkeeping.
 lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
   int cur = h->cur;
+  if (h->scalar) {
+    for (int j = 0; j < k; ++j) {
+      const int flags = j == k - 1 ? FLAG_REDUCE : 0;
+      if (lkp_status st = scalar_sweep(h, s, h->total_sweeps + j + 1, cur, 1 - cur, flags)) return st;
+      cur = 1 - cur;
+    }
+    return LKP_OK;
+  }
   for (int j = 0; j < k - 2; ++j) {
     if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, 0, nullptr, nullptr)) return st;
     cur = 1 - cur;
@@ -478,6 +529,7 @@ lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
 }
 
 lkp_status run_chunk(lkp_handle *h, int k, bool use_graph) {
+  if (h->scalar && h->total_sweeps == 0) use_graph = false;  // sweep 1 is a fill
   if (use_graph && k >= 2) {
     const long key = (long)k * 2 + h->cur;
     auto it = h->graphs.find(key);
@@ -521,7 +573,7 @@ lkp_status upload_coefficients(lkp_handle *h) {
     h->c32[i] = (float)h->c64[i];
     h->c32[Q + i] = (float)h->chi[i];
   }
-  if (h->precision == LKP_F32_IR) {
+  if (h->precision == LKP_F32_IR && !h->scalar) {
     HIP_TRY(hipMalloc(&h->phi_dev, Q * sizeof(double)));
     HIP_TRY(hipMemcpy(h->phi_dev, h->phi.data(), Q * sizeof(double), hipMemcpyHostToDevice));
   }
@@ -536,6 +588,89 @@ void release(lkp_handle *h) {
     if (p) (void)hipFree(p);
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   if (h->capture) (void)hipStreamDestroy(h->capture);
+}
+
+StencilParams stencil_params(const lkp_handle *h) {
+  StencilParams p{};
+  p.nx = (unsigned)h->n[0];
+  p.ny = (unsigned)h->n[1];
+  p.nz = (unsigned)h->n[2];
+  p.simple_wrap = h->simple_wrap ? 1u : 0u;
+  p.partials = h->partials;
+  return p;
+}
+
+// phi_i (omega = 1) as stencil weights in the given precision
+void stencil_weights(const lkp_handle *h, bool fp32, StencilParams *p) {
+  for (int i = 0; i < h->Q; ++i) {
+    if (fp32) p->coef.f[i] = (float)h->phi[i];
+    else p->coef.d[i] = h->phi[i];
+  }
+}
+
+unsigned partial_blocks(const lkp_handle *h) {
+  const unsigned a = sweep_blocks(h, 4);
+  const unsigned b = stencil_blocks(h->lattice, (unsigned)h->n[0], (unsigned)h->n[1], (unsigned)h->n[2]);
+  return std::max(a, b) + 8;
+}
+
+lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::vector<double> &S) {
+  (void)d;
+  const size_t n = h->ncells;
+  h->S_host = S;
+  const int64_t nb = partial_blocks(h);
+  h->footprint = 8 * (int64_t)n * (h->precision == LKP_F32 ? 3 : 4) + nb * NUM_NORMS * 8 + 4096;
+  if (h->precision == LKP_F32_IR) h->footprint += 4 * 4 * (int64_t)n;
+  HIP_TRY(hipMalloc(&h->norms_dev, NUM_NORMS * sizeof(double)));
+  HIP_TRY(hipHostMalloc(&h->norms_host, NUM_NORMS * sizeof(double), hipHostMallocDefault));
+  if (lkp_status st = ensure_partials(h, nb)) return st;
+  if (lkp_status st = upload_coefficients(h)) return st;
+  // G = sum_i chi_i S(x - v_i), once, with the FP64 stencil
+  double *S_dev = nullptr, *G_dev = nullptr;
+  HIP_TRY(hipMalloc(&S_dev, n * 8));
+  HIP_TRY(hipMalloc(&G_dev, n * 8));
+  HIP_TRY(hipMemcpy(S_dev, S.data(), n * 8, hipMemcpyHostToDevice));
+  StencilParams p = stencil_params(h);
+  for (int i = 0; i < h->Q; ++i) p.coef.d[i] = h->chi[i];
+  p.xin = S_dev;
+  p.xout = G_dev;
+  p.src = nullptr;
+  HIP_TRY(launch_stencil(h->lattice, SMODE_F64, 0, p, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipFree(S_dev));
+  const size_t fb = h->precision == LKP_F32 ? 4 : 8;
+  HIP_TRY(hipMalloc(&h->f[0], n * fb));
+  if (h->precision != LKP_F32_IR) HIP_TRY(hipMalloc(&h->f[1], n * fb));
+  if (h->precision == LKP_F32) {
+    HIP_TRY(hipMalloc(&h->S, n * 4));
+    HIP_TRY(launch_f64_to_f32(G_dev, (float *)h->S, n, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipFree(G_dev));
+    HIP_TRY(launch_fill_f32((float *)h->f[0], 0.0f, n, h->stream));
+  } else {
+    h->S = G_dev;
+    HIP_TRY(launch_fill_f64((double *)h->f[0], 0.0, n, h->stream));
+  }
+  if (h->precision == LKP_F32_IR) {
+    HIP_TRY(hipMalloc(&h->r32, n * 4));
+    HIP_TRY(hipMalloc(&h->d32[0], n * 4));
+    HIP_TRY(hipMalloc(&h->d32[1], n * 4));
+    HIP_TRY(hipMalloc(&h->S32, n * 4));
+    HIP_TRY(launch_f64_to_f32((const double *)h->S, h->S32, n, h->stream));
+    // residual of x = 0 is G
+    std::vector<double> G(n);
+    HIP_TRY(hipMemcpy(G.data(), h->S, n * 8, hipMemcpyDeviceToHost));
+    long double g2 = 0;
+    for (double v : G) g2 += (long double)v * v;
+    h->g_norm = (double)std::sqrt(g2);
+    const double one = 1.0;
+    HIP_TRY(hipMalloc(&h->phi_dev, sizeof(double)));
+    HIP_TRY(hipMemcpy(h->phi_dev, &one, sizeof(double), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->split = 1;
+  h->tuned = true;
+  return LKP_OK;
 }
 
 lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
@@ -592,6 +727,10 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   const double scale = h->cs2 * (h->tau_lb - 0.5);
   std::vector<double> S(n);
   for (size_t c = 0; c < n; ++c) S[c] = (remove ? s[c] - mean : s[c]) * scale;
+
+  // omega = 1 exactly: run the scalar stencil form unless populations are asked for
+  h->scalar = (h->omega == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP);
+  if (h->scalar) return create_scalar(d, h, S);
 
   // device memory
   const size_t Q = h->Q;
@@ -698,6 +837,17 @@ lkp_status lkp_step(lkp_handle *h, int64_t sweeps) {
   if (h->precision == LKP_F32_IR)
     return fail(LKP_ERR_UNSUPPORTED, "lkp_step drives the plain sweep; F32_IR handles use lkp_solve");
   if (h->group) return fail(LKP_ERR_STATE, "lkp_step: the handle is resident in a group");
+  if (h->scalar) {
+    int cur = h->cur;
+    for (int64_t j = 0; j < sweeps; ++j) {
+      if (lkp_status st = scalar_sweep(h, h->stream, h->total_sweeps + j + 1, cur, 1 - cur, 0)) return st;
+      cur = 1 - cur;
+    }
+    h->cur = cur;
+    h->total_sweeps += sweeps;
+    HIP_TRY(hipGetLastError());
+    return LKP_OK;
+  }
   if (lkp_status st = tune_split(h)) return st;
   int cur = h->cur;
   for (int64_t j = 0; j < sweeps - 1; ++j) {
@@ -752,6 +902,23 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
       }
       // one chunk of K inner FP32 sweeps, norms on the last two
       const int P = h->split;
+      if (h->scalar) {
+        for (int j = 0; j < K; ++j) {
+          StencilParams p = stencil_params(h);
+          stencil_weights(h, true, &p);
+          p.xin = h->d32[h->ir.dc];
+          p.xout = h->d32[1 - h->ir.dc];
+          p.src = h->ir.outer == 0 ? (const void *)h->S32 : (const void *)h->r32;
+          HIP_TRY(launch_stencil(h->lattice, SMODE_F32, j == K - 1 ? FLAG_REDUCE : 0, p, h->stream));
+          h->ir.dc = 1 - h->ir.dc;
+        }
+        h->total_sweeps += K;
+        if (lkp_status st = finish_norms(h, scalar_blocks(h), h->norms_dev, h->stream)) return st;
+        if (lkp_status st = read_back(h, nr)) return st;
+        result = ir_after_inner(h, nr, K, *o, &rep);
+        if (result) break;
+        continue;
+      }
       for (int j = 0; j < K; ++j) {
         SweepParams p = ir_inner_params(h, P);
         int flags = 0;
@@ -783,8 +950,14 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
                                   : (h->phi_sweep[a] == h->total_sweeps && h->total_sweeps >= 1);
       if (lkp_status st = run_chunk(h, k, o->use_graph != 0)) return st;
       double nr[NUM_NORMS];
-      if (lkp_status st = read_norms(h, sweep_blocks(h, h->split), nr)) return st;
-      result = track_check(h, nr, prev_ok, *o, &rep, &converged);
+      if (h->scalar) {
+        if (h->total_sweeps < 2) continue;  // the only sweep was the first (Phi = 0)
+        if (lkp_status st = read_norms(h, scalar_blocks(h), nr)) return st;
+        result = track_check(h, nr, true, *o, &rep, &converged);
+      } else {
+        if (lkp_status st = read_norms(h, sweep_blocks(h, h->split), nr)) return st;
+        result = track_check(h, nr, prev_ok, *o, &rep, &converged);
+      }
       if (result) break;
     }
   }
@@ -803,6 +976,28 @@ lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r) {
   if (!h || !r) return fail(LKP_ERR_ARG, "lkp_residual: null argument");
   std::memset(r, 0, sizeof *r);
   r->sweeps = h->total_sweeps;
+  if (h->scalar) {
+    if (h->total_sweeps < 1) return fail(LKP_ERR_STATE, "lkp_residual needs at least one sweep");
+    const bool fp32 = h->precision == LKP_F32;
+    const int x = h->precision == LKP_F32_IR ? 0 : h->cur;
+    StencilParams p = stencil_params(h);
+    stencil_weights(h, fp32, &p);
+    p.xin = h->f[x];
+    p.xout = h->precision == LKP_F32_IR ? (void *)h->r32 : h->f[1 - h->cur];
+    p.src = h->S;
+    HIP_TRY(launch_stencil(h->lattice, fp32 ? SMODE_F32 : SMODE_RESID, FLAG_REDUCE, p, h->stream));
+    double nr[NUM_NORMS];
+    if (lkp_status st = read_norms(h, scalar_blocks(h), nr)) return st;
+    double phi2 = 0;
+    for (double v : h->phi) phi2 += v * v;
+    r->max_change = nr[NORM_MAX_DPHI];
+    r->l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
+    // populations are phi_i Phi + chi_i S, so their residual is phi_i (Phi' - Phi)
+    r->pop_residual_l2 = fp32 ? NAN : std::sqrt(phi2) * r->l2_change;
+    r->phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
+    r->mass = nr[NORM_SUM_PHI];
+    return LKP_OK;
+  }
   const int last = h->phi_last;
   if (h->total_sweeps < 1 || h->phi_sweep[last] != h->total_sweeps)
     return fail(LKP_ERR_STATE, "lkp_residual needs the Phi of the last sweep (run a sweep first)");
@@ -840,6 +1035,26 @@ lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r) {
 
 lkp_status lkp_get_phi(lkp_handle *h, double *dst, int32_t dst_is_device) {
   if (!h || !dst) return fail(LKP_ERR_ARG, "lkp_get_phi: null argument");
+  if (h->scalar) {
+    if (h->total_sweeps < 1) return fail(LKP_ERR_STATE, "no Phi before the first sweep");
+    const size_t n = h->ncells;
+    const void *src = h->precision == LKP_F32_IR ? h->f[0] : h->f[h->cur];
+    if (h->precision == LKP_F32) {
+      double *tmp = dst;
+      if (!dst_is_device) HIP_TRY(hipMalloc(&tmp, n * 8));
+      HIP_TRY(launch_f32_to_f64((const float *)src, tmp, n, h->stream));
+      if (!dst_is_device) {
+        HIP_TRY(hipMemcpyAsync(dst, tmp, n * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(hipFree(tmp));
+      }
+    } else {
+      HIP_TRY(hipMemcpyAsync(dst, src, n * 8, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LKP_OK;
+  }
   const int last = h->phi_last;
   if (h->phi_sweep[last] != h->total_sweeps || h->total_sweeps < 1)
     return fail(LKP_ERR_STATE, "no Phi for the current state (run a sweep first)");
@@ -852,6 +1067,17 @@ lkp_status lkp_get_phi(lkp_handle *h, double *dst, int32_t dst_is_device) {
 
 lkp_status lkp_get_populations(lkp_handle *h, double *dst, int32_t dst_is_device) {
   if (!h || !dst) return fail(LKP_ERR_ARG, "lkp_get_populations: null argument");
+  if (h->scalar) {  // f*_i = phi_i Phi + chi_i S after any sweep, 0 before the first
+    const size_t n = h->ncells, Q = h->Q;
+    std::vector<double> phi(n, 0.0), f(Q * n, 0.0);
+    if (h->total_sweeps >= 1) {
+      if (lkp_status st = lkp_get_phi(h, phi.data(), 0)) return st;
+      for (size_t i = 0; i < Q; ++i)
+        for (size_t c = 0; c < n; ++c) f[i * n + c] = h->phi[i] * phi[c] + h->chi[i] * h->S_host[c];
+    }
+    HIP_TRY(hipMemcpy(dst, f.data(), Q * n * 8, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    return LKP_OK;
+  }
   const size_t QN = (size_t)h->Q * h->ncells;
   if (h->precision == LKP_F32) {
     double *tmp = dst;
@@ -874,6 +1100,9 @@ lkp_status lkp_get_populations(lkp_handle *h, double *dst, int32_t dst_is_device
 
 lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_device) {
   if (!h || !src) return fail(LKP_ERR_ARG, "lkp_set_populations: null argument");
+  if (h->scalar)
+    return fail(LKP_ERR_UNSUPPORTED, "the tau_lb = 1 stencil form keeps Phi only; create the handle "
+                                     "with LKP_FLAG_POPULATION_SWEEP to set populations");
   const size_t QN = (size_t)h->Q * h->ncells;
   const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (h->precision == LKP_F32) {
@@ -922,6 +1151,8 @@ lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info) {
   info->Q = h->Q;
   info->precision = h->precision;
   info->velocity_groups = h->split;
+  info->scalar_stencil = h->scalar ? 1 : 0;
+  info->reserved = 0;
   for (int a = 0; a < 3; ++a) info->n[a] = h->n[a];
   info->tau_lb = h->tau_lb;
   info->omega = h->omega;

@@ -79,6 +79,11 @@ struct lkp_handle {
   void *S = nullptr;          // scaled source in the sweep precision (double for IR)
   float *S32 = nullptr;       // IR: the scaled source rounded to FP32 (first solve)
   double g_norm = 0.0;        // IR: ||chi_i S||_2, the residual of x = 0
+  // omega = 1: the state is Phi alone and a sweep is the stencil
+  // Phi' = sum_i phi_i Phi(x - v_i) + G.  f[0], f[1] (n values each) hold Phi,
+  // S holds G (not S), r32 / d32 / S32 are n-sized (IR: R, D, G in FP32).
+  bool scalar = false;
+  std::vector<double> S_host;  // the scaled source S (to rebuild populations)
   double *phi_dev = nullptr;  // phi_i on the device (IR mass projection)
   float *r32 = nullptr;
   float *d32[2] = {nullptr, nullptr};

@@ -109,6 +109,29 @@ hipError_t launch_sweep_batch(int lattice, int mode, int P, int flags, const voi
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_stencil(int lattice, int smode, int flags, const StencilParams &p, hipStream_t s) {
+  switch (lattice) {
+    case D1Q5: return launch_stencil_tu<D1Q5>(smode, flags, p, s);
+    case D1Q9: return launch_stencil_tu<D1Q9>(smode, flags, p, s);
+    case D1Q13: return launch_stencil_tu<D1Q13>(smode, flags, p, s);
+    case D2Q5: return launch_stencil_tu<D2Q5>(smode, flags, p, s);
+    case D2Q9: return launch_stencil_tu<D2Q9>(smode, flags, p, s);
+    case D2Q25: return launch_stencil_tu<D2Q25>(smode, flags, p, s);
+    case D2Q81: return launch_stencil_tu<D2Q81>(smode, flags, p, s);
+    case D2Q169: return launch_stencil_tu<D2Q169>(smode, flags, p, s);
+    case D3Q111: return launch_stencil_tu<D3Q111>(smode, flags, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz) {
+  const int dim = velocity_table(lattice).dim;
+  const unsigned tx = dim == 1 ? 256 : (dim == 2 ? 64 : 32);
+  const unsigned ty = dim == 1 ? 1 : (dim == 2 ? 16 : 8);
+  const unsigned tz = dim == 3 ? 4 : 1;
+  return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+}
+
 hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, out);
   return hipGetLastError();

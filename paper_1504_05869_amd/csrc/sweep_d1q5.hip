@@ -1,7 +1,9 @@
 // Fused sweep kernels for D1Q5 (all precision modes and velocity splits).
+#include "stencil_impl.hpp"
 #include "sweep_impl.hpp"
 
 namespace lkp {
 template hipError_t launch_lattice_tu<D1Q5>(int, int, int, SweepParams, hipStream_t);
 template hipError_t launch_batch_tu<D1Q5>(int, int, int, const void *, hipStream_t);
+template hipError_t launch_stencil_tu<D1Q5>(int, int, const StencilParams &, hipStream_t);
 }  // namespace lkp

@@ -114,9 +114,10 @@ def test_converged_f64_matches_spectral(lattice, shape, tau):
 
 
 def test_config1_stop_rule_matches_oracle():
-    """64x64 D2Q5, tau_lb = 1, max|dPhi| < 1e-10 checked every sweep."""
+    """64x64 D2Q5, tau_lb = 1, max|dPhi| < 1e-10 checked every sweep, through
+    the population sweep (the tau_lb = 1 stencil form has its own test)."""
     s = W.sine_product((64, 64))
-    with lkp.Problem(s, "D2Q5", 1, tau_lb=1.0) as p:
+    with lkp.Problem(s, "D2Q5", 1, tau_lb=1.0, population_sweep=True) as p:
         rep = p.solve(tol_maxchange=1e-10, check_every=1, max_sweeps=100000)
         phi = p.phi_host()
     phi_ref, sweeps_ref, _ = SW.solve_maxchange(SW.Problem("D2Q5", 1, 1.0, s), 1e-10, 100000)

@@ -101,6 +101,16 @@ def test_alone_equals_mix_bitwise(lattice, order, precision, split, specs):
         assert err <= (1e-8 if precision == "f64" else 2e-7)
 
 
+def test_group_rejects_stencil_form_handles():
+    """tau_lb = 1 handles keep Phi only and are driven by lkp_solve."""
+    g = lkp.Group("D2Q25", 3, "f64")
+    with lkp.Problem(_source((16, 16), 1), "D2Q25", 3, tau_lb=1.0) as p:
+        with pytest.raises(lkp.LkpError) as ei:
+            g.add(p, tol_rel_l2=1e-8)
+        assert ei.value.name == "LKP_ERR_UNSUPPORTED"
+    g.close()
+
+
 def test_group_rejects_other_class_and_stream():
     s = _source((16, 16), 1)
     g = lkp.Group("D2Q81", 5, "f64")
@@ -123,7 +133,7 @@ def test_group_rejects_other_class_and_stream():
 def test_group_member_limit_reported():
     s = _source((24, 24), 2)
     g = lkp.Group("D2Q25", 3, "f64")
-    with lkp.Problem(s, "D2Q25", 3, tau_lb=1.0) as p:
+    with lkp.Problem(s, "D2Q25", 3, tau_lb=1.5) as p:
         g.add(p, tol_rel_l2=1e-14, max_sweeps=40)
         reps = []
         for _ in range(5):
