@@ -106,7 +106,7 @@ struct StencilParams {
   double *partials;  // NUM_NORMS per block (FLAG_REDUCE)
   unsigned nx, ny, nz;
   unsigned simple_wrap;
-  union {            // stencil weights per velocity (phi_i, or chi_i to form G)
+  union {            // stencil weights per velocity orbit (phi, or chi to form G)
     double d[MAXQ];
     float f[MAXQ];
   } coef;

@@ -130,6 +130,47 @@ constexpr int max_component(const VelTable& t, int axis) {
   return m;
 }
 
+// Orbit of a velocity under axis permutations and sign changes: the sorted
+// absolute components.  Weights (tensor products of 1D weights, or D3Q111
+// shell weights) and the radial Hermite factors of phi_i and chi_i are all
+// constant on an orbit, so stencil weights need one value per orbit.
+constexpr int orbit_key(const VelTable &t, int i) {
+  int a = t.v[i][0] < 0 ? -t.v[i][0] : t.v[i][0];
+  int b = t.v[i][1] < 0 ? -t.v[i][1] : t.v[i][1];
+  int c = t.v[i][2] < 0 ? -t.v[i][2] : t.v[i][2];
+  if (a < b) { const int x = a; a = b; b = x; }
+  if (b < c) { const int x = b; b = c; c = x; }
+  if (a < b) { const int x = a; a = b; b = x; }
+  return (a * 16 + b) * 16 + c;
+}
+
+// Index of velocity i's orbit, numbered by first appearance in the table.
+constexpr int orbit_index(const VelTable &t, int i) {
+  const int key = orbit_key(t, i);
+  int n = 0;
+  for (int j = 0; j < t.q; ++j) {
+    const int kj = orbit_key(t, j);
+    bool first = true;
+    for (int m = 0; m < j; ++m)
+      if (orbit_key(t, m) == kj) first = false;
+    if (!first) continue;
+    if (kj == key) return n;
+    ++n;
+  }
+  return -1;
+}
+
+constexpr int num_orbits(const VelTable &t) {
+  int n = 0;
+  for (int j = 0; j < t.q; ++j) {
+    bool first = true;
+    for (int m = 0; m < j; ++m)
+      if (orbit_key(t, m) == orbit_key(t, j)) first = false;
+    if (first) ++n;
+  }
+  return n;
+}
+
 // Compile-time view of one set, for kernel templates.
 template <int ID>
 struct Lattice {
@@ -144,5 +185,7 @@ struct Lattice {
 static_assert(velocity_table(D3Q111).q == 111, "Table vector2 lists 111 velocities");
 static_assert(velocity_table(D2Q169).q == 169, "");
 static_assert(velocity_table(D2Q81).q == 81, "");
+static_assert(num_orbits(velocity_table(D3Q111)) == 10, "Table vector2 has ten weight classes");
+static_assert(num_orbits(velocity_table(D2Q169)) <= 32, "stencil weights travel in scalar registers");
 
 }  // namespace lkp

@@ -168,7 +168,8 @@ lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
     p.nz = (unsigned)h->n[2];
     p.simple_wrap = h->simple_wrap ? 1u : 0u;
     p.partials = h->partials;
-    for (int i = 0; i < h->Q; ++i) p.coef.d[i] = h->phi[i];
+    const VelTable T = velocity_table(h->lattice);
+    for (int i = 0; i < T.q; ++i) p.coef.d[orbit_index(T, i)] = h->phi[i];
     p.xin = h->f[0];
     p.xout = h->r32;
     p.src = h->S;
@@ -600,12 +601,20 @@ StencilParams stencil_params(const lkp_handle *h) {
   return p;
 }
 
+// Per-orbit stencil weights from per-velocity values (equal on an orbit).
+void orbit_weights(const lkp_handle *h, const std::vector<double> &per_velocity, bool fp32,
+                   StencilParams *p) {
+  const VelTable T = velocity_table(h->lattice);
+  for (int i = 0; i < T.q; ++i) {
+    const int o = orbit_index(T, i);
+    if (fp32) p->coef.f[o] = (float)per_velocity[i];
+    else p->coef.d[o] = per_velocity[i];
+  }
+}
+
 // phi_i (omega = 1) as stencil weights in the given precision
 void stencil_weights(const lkp_handle *h, bool fp32, StencilParams *p) {
-  for (int i = 0; i < h->Q; ++i) {
-    if (fp32) p->coef.f[i] = (float)h->phi[i];
-    else p->coef.d[i] = h->phi[i];
-  }
+  orbit_weights(h, h->phi, fp32, p);
 }
 
 unsigned partial_blocks(const lkp_handle *h) {
@@ -616,6 +625,16 @@ unsigned partial_blocks(const lkp_handle *h) {
 
 lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::vector<double> &S) {
   (void)d;
+  {  // phi_i and chi_i must be equal on every orbit for per-orbit stencil weights
+    const VelTable T = velocity_table(h->lattice);
+    std::vector<int> rep(num_orbits(T), -1);
+    for (int i = 0; i < T.q; ++i) {
+      const int o = orbit_index(T, i);
+      if (rep[o] < 0) rep[o] = i;
+      else if (h->phi[i] != h->phi[rep[o]] || h->chi[i] != h->chi[rep[o]])
+        return fail(LKP_ERR_HIP, "coefficients differ within a velocity orbit");
+    }
+  }
   const size_t n = h->ncells;
   h->S_host = S;
   const int64_t nb = partial_blocks(h);
@@ -631,7 +650,7 @@ lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::ve
   HIP_TRY(hipMalloc(&G_dev, n * 8));
   HIP_TRY(hipMemcpy(S_dev, S.data(), n * 8, hipMemcpyHostToDevice));
   StencilParams p = stencil_params(h);
-  for (int i = 0; i < h->Q; ++i) p.coef.d[i] = h->chi[i];
+  orbit_weights(h, h->chi, false, &p);
   p.xin = S_dev;
   p.xout = G_dev;
   p.src = nullptr;

@@ -118,15 +118,23 @@ __global__ void __launch_bounds__(256) k_stencil(StencilParams p) {
             if constexpr (vy >= -VMY && vy <= VMY) {
               constexpr int i = vel_index(L::table, vx, vy, vz);
               if constexpr (i >= 0) {
+                constexpr int o = orbit_index(L::table, i);
                 TC c;
-                if constexpr (sizeof(TC) == 8) c = (TC)p.coef.d[i];
-                else c = (TC)p.coef.f[i];
+                if constexpr (sizeof(TC) == 8) c = (TC)p.coef.d[o];
+                else c = (TC)p.coef.f[o];
                 acc[k] = acc[k] + c * v;
               }
             }
           });
         }
       });
+      // Compiler-only fence (emits nothing): the accumulators pass through it
+      // and it clobbers memory, so this column's arithmetic cannot sink below
+      // it and the next column's LDS reads cannot rise above it.  Without it
+      // the scheduler issues every LDS read of the stencil first and spills
+      // the staged values to scratch.
+#pragma unroll
+      for (int k = 0; k < T::CY; ++k) asm volatile("" : "+v"(acc[k]) : : "memory");
     });
   });
 
