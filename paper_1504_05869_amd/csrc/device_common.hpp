@@ -4,24 +4,41 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "kernels.hpp"
 
 namespace lkp {
 namespace dev {
 
+// f(integral_constant<B>), ..., f(integral_constant<E - 1>) as one fold
+// expression (no recursion: one instantiation per call site).
+template <int B, class F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, B + I>{}), ...);
+}
+
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F &&f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
+  if constexpr (B < E) static_for_seq<B>(f, std::make_integer_sequence<int, E - B>{});
 }
 
 __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
   const unsigned q = nb >> 3, r = nb & 7u;
   const unsigned xcd = b & 7u, k = b >> 3;
   return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// Runs of R consecutive blocks per XCD with the 8 XCDs on adjacent runs:
+// block b = 8 k + xcd (dealt round-robin) becomes ((k / R) * 8 + xcd) * R +
+// k % R.  The chip as a whole still walks one compact window of the grid,
+// while neighbouring blocks inside a run share their XCD's L2.  Blocks past
+// the last whole group of 8 R keep their number.
+__device__ __forceinline__ unsigned xcd_runs(unsigned b, unsigned nb, unsigned R) {
+  const unsigned full = nb / (8u * R) * (8u * R);
+  if (b >= full) return b;
+  const unsigned xcd = b & 7u, k = b >> 3;
+  return ((k / R) * 8u + xcd) * R + k % R;
 }
 
 // (x - d) mod n for |d| <= VM.  simple: n >= VM, one correction suffices.

@@ -112,6 +112,15 @@ struct StencilParams {
   } coef;
 };
 
+// Output cells of one stencil block (256 threads): 1D 256; 2D 64 x 16;
+// 3D 64 x 16 x 16 (the block marches through its 16 z-planes).
+struct StencilShape {
+  unsigned tx, ty, tz;
+};
+constexpr StencilShape stencil_shape(int dim) {
+  return dim == 1 ? StencilShape{256, 1, 1} : (dim == 2 ? StencilShape{64, 16, 1} : StencilShape{64, 16, 16});
+}
+
 template <int LID>
 hipError_t launch_stencil_tu(int smode, int flags, const StencilParams &p, hipStream_t s);
 

@@ -144,30 +144,46 @@ constexpr int orbit_key(const VelTable &t, int i) {
   return (a * 16 + b) * 16 + c;
 }
 
-// Index of velocity i's orbit, numbered by first appearance in the table.
-constexpr int orbit_index(const VelTable &t, int i) {
-  const int key = orbit_key(t, i);
-  int n = 0;
-  for (int j = 0; j < t.q; ++j) {
-    const int kj = orbit_key(t, j);
-    bool first = true;
-    for (int m = 0; m < j; ++m)
-      if (orbit_key(t, m) == kj) first = false;
-    if (!first) continue;
-    if (kj == key) return n;
-    ++n;
+// Lookup tables of one set: velocity index by components (-1 where the set
+// has no such velocity; components lie in [-6, 6]) and orbit index by
+// velocity.  Built once per set, so kernel templates look them up in
+// constant time instead of searching the table.
+struct VelMaps {
+  int vidx[13][13][13];
+  int orbit[MAXQ];
+};
+
+constexpr VelMaps build_maps(const VelTable &t) {
+  VelMaps m{};
+  for (int a = 0; a < 13; ++a)
+    for (int b = 0; b < 13; ++b)
+      for (int c = 0; c < 13; ++c) m.vidx[a][b][c] = -1;
+  int key[MAXQ] = {};
+  for (int i = 0; i < t.q; ++i) {
+    m.vidx[t.v[i][0] + 6][t.v[i][1] + 6][t.v[i][2] + 6] = i;
+    key[i] = orbit_key(t, i);
   }
-  return -1;
+  int first[MAXQ] = {};  // key of orbit n
+  int n = 0;
+  for (int i = 0; i < t.q; ++i) {
+    int o = -1;
+    for (int j = 0; j < n; ++j)
+      if (first[j] == key[i]) o = j;
+    if (o < 0) {
+      first[n] = key[i];
+      o = n++;
+    }
+    m.orbit[i] = o;
+  }
+  return m;
 }
 
+// Number of orbits of a set (orbits are numbered by first appearance).
 constexpr int num_orbits(const VelTable &t) {
+  const VelMaps m = build_maps(t);
   int n = 0;
-  for (int j = 0; j < t.q; ++j) {
-    bool first = true;
-    for (int m = 0; m < j; ++m)
-      if (orbit_key(t, m) == orbit_key(t, j)) first = false;
-    if (first) ++n;
-  }
+  for (int i = 0; i < t.q; ++i)
+    if (m.orbit[i] + 1 > n) n = m.orbit[i] + 1;
   return n;
 }
 
@@ -180,6 +196,14 @@ struct Lattice {
   static constexpr int VMX = max_component(table, 0);
   static constexpr int VMY = max_component(table, 1);
   static constexpr int VMZ = max_component(table, 2);
+  static constexpr VelMaps maps = build_maps(table);
+  // index of velocity (vx, vy, vz), -1 if absent
+  static constexpr int vel(int vx, int vy, int vz) {
+    return (vx < -6 || vx > 6 || vy < -6 || vy > 6 || vz < -6 || vz > 6)
+               ? -1
+               : maps.vidx[vx + 6][vy + 6][vz + 6];
+  }
+  static constexpr int orbit(int i) { return maps.orbit[i]; }
 };
 
 static_assert(velocity_table(D3Q111).q == 111, "Table vector2 lists 111 velocities");

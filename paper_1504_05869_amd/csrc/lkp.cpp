@@ -169,7 +169,8 @@ lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
     p.simple_wrap = h->simple_wrap ? 1u : 0u;
     p.partials = h->partials;
     const VelTable T = velocity_table(h->lattice);
-    for (int i = 0; i < T.q; ++i) p.coef.d[orbit_index(T, i)] = h->phi[i];
+    const VelMaps M = build_maps(T);
+    for (int i = 0; i < T.q; ++i) p.coef.d[M.orbit[i]] = h->phi[i];
     p.xin = h->f[0];
     p.xout = h->r32;
     p.src = h->S;
@@ -605,8 +606,9 @@ StencilParams stencil_params(const lkp_handle *h) {
 void orbit_weights(const lkp_handle *h, const std::vector<double> &per_velocity, bool fp32,
                    StencilParams *p) {
   const VelTable T = velocity_table(h->lattice);
+  const VelMaps M = build_maps(T);
   for (int i = 0; i < T.q; ++i) {
-    const int o = orbit_index(T, i);
+    const int o = M.orbit[i];
     if (fp32) p->coef.f[o] = (float)per_velocity[i];
     else p->coef.d[o] = per_velocity[i];
   }
@@ -627,9 +629,10 @@ lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::ve
   (void)d;
   {  // phi_i and chi_i must be equal on every orbit for per-orbit stencil weights
     const VelTable T = velocity_table(h->lattice);
+    const VelMaps M = build_maps(T);
     std::vector<int> rep(num_orbits(T), -1);
     for (int i = 0; i < T.q; ++i) {
-      const int o = orbit_index(T, i);
+      const int o = M.orbit[i];
       if (rep[o] < 0) rep[o] = i;
       else if (h->phi[i] != h->phi[rep[o]] || h->chi[i] != h->chi[rep[o]])
         return fail(LKP_ERR_HIP, "coefficients differ within a velocity orbit");

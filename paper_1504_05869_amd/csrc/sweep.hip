@@ -125,11 +125,8 @@ hipError_t launch_stencil(int lattice, int smode, int flags, const StencilParams
 }
 
 unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz) {
-  const int dim = velocity_table(lattice).dim;
-  const unsigned tx = dim == 1 ? 256 : (dim == 2 ? 64 : 32);
-  const unsigned ty = dim == 1 ? 1 : (dim == 2 ? 16 : 8);
-  const unsigned tz = dim == 3 ? 4 : 1;
-  return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+  const StencilShape sh = stencil_shape(velocity_table(lattice).dim);
+  return ((nx + sh.tx - 1) / sh.tx) * ((ny + sh.ty - 1) / sh.ty) * ((nz + sh.tz - 1) / sh.tz);
 }
 
 hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, hipStream_t s) {

