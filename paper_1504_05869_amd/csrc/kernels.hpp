@@ -113,12 +113,12 @@ struct StencilParams {
 };
 
 // Output cells of one stencil block (256 threads): 1D 256; 2D 64 x 16;
-// 3D 64 x 16 x 16 (the block marches through its 16 z-planes).
+// 3D 64 x 8 x 32 (the block marches through its 32 z-planes).
 struct StencilShape {
   unsigned tx, ty, tz;
 };
 constexpr StencilShape stencil_shape(int dim) {
-  return dim == 1 ? StencilShape{256, 1, 1} : (dim == 2 ? StencilShape{64, 16, 1} : StencilShape{64, 16, 16});
+  return dim == 1 ? StencilShape{256, 1, 1} : (dim == 2 ? StencilShape{64, 16, 1} : StencilShape{64, 8, 32});
 }
 
 template <int LID>

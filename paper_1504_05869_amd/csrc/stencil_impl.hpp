@@ -183,9 +183,11 @@ __global__ void __launch_bounds__(256) k_stencil(StencilParams p) {
 // of 2 VMZ + 1 planes x CY rows.  Output plane m is complete once input plane
 // m + VMZ has been consumed.  The next input plane is fetched into registers
 // while the current one is consumed, and the products are fused
-// multiply-adds.  For D3Q111 with CY = 4 an output cell costs 16.5 LDS reads
-// (72.5 when the whole 3D tile is staged and read per z-offset) and the
-// staging reads 1.5 input values per output (5.2 for a 32 x 8 x 4 tile).
+// multiply-adds.  For D3Q111 with CY = 2 an output cell costs 26 LDS reads
+// (72.5 when a whole 32 x 8 x 4 tile plus halo is staged and read per
+// z-offset) and staging reads 1.9 input values per output (5.2).  CY = 2 and
+// 32 planes per block measured fastest among CY in {2, 4, 6} and 8 to 32
+// planes, at 256^3 and 512^3.
 template <int SM> struct FmaT;
 template <> struct FmaT<SMODE_F64> {
   static __device__ __forceinline__ double f(double a, double b, double c) { return __builtin_fma(a, b, c); }
