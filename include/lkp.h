@@ -72,7 +72,12 @@ typedef enum lkp_lattice {
 typedef enum lkp_precision {
   LKP_F64 = 0,    /* FP64 populations, FP64 everything */
   LKP_F32 = 1,    /* FP32 populations and sweep (FP64 moment sum and norms), no refinement */
-  LKP_F32_IR = 2  /* FP32 inner sweeps inside FP64 iterative refinement on the population state */
+  LKP_F32_IR = 2,    /* FP32 inner sweeps inside FP64 iterative refinement on the population state */
+  LKP_BF16DEV_IR = 3 /* ablation: inner sweeps store each population as phi_i Phi + n_i with the
+                      * deviation n_i in BF16 and Phi in FP32 (4Q + 12 bytes per cell and sweep
+                      * instead of 12Q for FP32), inside the same FP64 refinement; the first
+                      * inner solve is the plain BF16-deviation sweep.  Not available in the
+                      * tau_lb = 1 stencil form (there n_i = chi_i S exactly) nor in groups. */
 } lkp_precision;
 
 /* At tau_lb = 1 (omega = 1) the collision forgets the populations: after a

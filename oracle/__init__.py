@@ -21,6 +21,8 @@ path:
 * ``spectral`` -- the exact fixed point of that iteration on a periodic grid,
   one Fourier mode at a time.
 * ``dense``    -- the same fixed point by a dense linear solve on tiny grids.
+* ``bf16dev``  -- the same sweep with the post-collision state stored as an
+  FP32 moment and BF16 deviations (storage-precision ablation).
 
 Every function with no independent pin says "parity unpinned" in its
 docstring; at present there is none.

@@ -15,7 +15,7 @@ LATTICES = ["d1q5", "d1q9", "d1q13", "d2q5", "d2q9", "d2q25", "d2q81", "d2q169",
 # largest first so the parallel build finishes early
 SOURCES = (["sweep_d2q169.hip", "sweep_d3q111.hip", "sweep_d2q81.hip"]
            + [f"sweep_{l}.hip" for l in LATTICES if l not in ("d2q169", "d3q111", "d2q81")]
-           + ["sweep.hip", "lkp.cpp", "group.cpp", "constants.cpp"])
+           + ["sweep.hip", "dev.hip", "lkp.cpp", "group.cpp", "constants.cpp"])
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

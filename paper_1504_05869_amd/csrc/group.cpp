@@ -246,6 +246,8 @@ lkp_status lkp_group_create(int32_t lattice, int32_t order, int32_t precision, v
   if (!out) return fail(LKP_ERR_ARG, "null output group pointer");
   *out = nullptr;
   if (lattice < 0 || lattice >= LKP_NUM_LATTICES) return fail(LKP_ERR_ARG, "unknown lattice");
+  if (precision == LKP_BF16DEV_IR)
+    return fail(LKP_ERR_UNSUPPORTED, "groups batch F64, F32 and F32_IR problems (BF16DEV_IR is an ablation)");
   if (precision < LKP_F64 || precision > LKP_F32_IR) return fail(LKP_ERR_ARG, "unknown precision");
   const VelTable T = velocity_table(lattice);
   if (order > T.max_order || (order != 1 && order != 3 && order != 5 && order != 7))

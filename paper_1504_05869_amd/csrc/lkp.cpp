@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "constants.hpp"
+#include "dev_kernels.hpp"
 #include "kernels.hpp"
 #include "runtime.hpp"
 
@@ -200,7 +201,12 @@ lkp_status ir_begin_inner(lkp_handle *h, const lkp_solve_opts &o) {
   IrState &s = h->ir;
   if (s.phase == IR_START) s.rnorm = h->g_norm;  // residual of x = 0
   const size_t QN = (size_t)(h->scalar ? 1 : h->Q) * h->ncells;
-  LKP_HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
+  if (h->bf16dev()) {
+    LKP_HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(h->dn[0]), 0u, (QN + 1) / 2, h->stream));
+    LKP_HIP_TRY(launch_fill_f32(h->dphi[0], 0.0f, h->ncells, h->stream));
+  } else {
+    LKP_HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
+  }
   s.dc = 0;
   // Inner accuracy: as asked, or just enough to close the remaining gap
   // (30 % margin), never below the FP32 sweep's own floor (~1e-7 relative).
@@ -285,18 +291,29 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
   const double est = (s.rate > 0 && s.rate < 1) ? l2 * s.rate / (1 - s.rate) : 1e300;
   // FP32 sweeps cannot bring the correction closer than about u32 / (1 - rho)
   // of its size (rounding of each sweep, amplified by the slow contraction);
-  // stop there rather than sweep on without gaining accuracy.
-  const double floor32 = (s.rate > 0 && s.rate < 1) ? 2.0 * 5.96e-8 / (1 - s.rate) : 0.0;
+  // stop there rather than sweep on without gaining accuracy.  BF16 deviation
+  // storage has no such simple floor (its rounding is relative to the
+  // deviation, not the population): there the stall rule decides.
+  const double floor32 =
+      (!h->bf16dev() && s.rate > 0 && s.rate < 1) ? 2.0 * 5.96e-8 / (1 - s.rate) : 0.0;
   const double goal = std::max(s.inner_tol, floor32);
   if (!(s.corr == 0 || est <= goal * s.corr || s.stall >= 2)) return LKP_OK;
   // inner solve done: x += d - phi_i mean(d), FP64 (scalar state: x += d - mean(d))
   const int q = h->scalar ? 1 : h->Q;
   const size_t QN = (size_t)q * h->ncells;
   unsigned nb = 0;
-  LKP_HIP_TRY(launch_sum_f32(h->d32[s.dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream));
-  LKP_HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
-  LKP_HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[s.dc], h->phi_dev, h->norms_dev, q,
-                               h->ncells, h->stream));
+  if (h->bf16dev()) {  // d_i = phi_i Phi + n_i
+    LKP_HIP_TRY(launch_dev_sum(h->dn[s.dc], h->dphi[s.dc], (unsigned)q, h->ncells, h->partials,
+                               (unsigned)h->partial_cap, &nb, h->stream));
+    LKP_HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
+    LKP_HIP_TRY(launch_ir_update_dev((double *)h->f[0], h->dn[s.dc], h->dphi[s.dc], h->phi_dev,
+                                     h->norms_dev, (unsigned)q, h->ncells, h->stream));
+  } else {
+    LKP_HIP_TRY(launch_sum_f32(h->d32[s.dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream));
+    LKP_HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
+    LKP_HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[s.dc], h->phi_dev, h->norms_dev, q,
+                                 h->ncells, h->stream));
+  }
   s.outer += 1;
   s.corr_prev = s.corr;
   s.rnorm_prev = s.rnorm;
@@ -311,6 +328,10 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
 lkp_status tune_split(lkp_handle *h) {
   if (h->tuned) return LKP_OK;
   h->tuned = true;
+  if (h->bf16dev()) {  // one deviation-sweep variant per lattice
+    h->split = dev_split(h->lattice);
+    return LKP_OK;
+  }
   const int mode = h->precision == LKP_F32_IR ? MODE_INNER : h->mode();
   const long key = tune_key(h->lattice, mode, h->ncells);
   // LKP_SPLIT forces a split when that variant is built (tests, experiments)
@@ -387,7 +408,11 @@ int64_t footprint_of(int precision, int Q, int64_t ncells) {
   int64_t b = 3 * 8 * ncells + nb * NUM_NORMS * 8 + 4096;  // S + 2 Phi + partials + misc
   if (precision == LKP_F64) b += 2 * 8 * (int64_t)Q * ncells;
   else if (precision == LKP_F32) b += 2 * 4 * (int64_t)Q * ncells;
-  else b += 8 * (int64_t)Q * ncells + 3 * 4 * (int64_t)Q * ncells + 4 * ncells;  // x, r, 2 d, S32
+  else if (precision == LKP_F32_IR)
+    b += 8 * (int64_t)Q * ncells + 3 * 4 * (int64_t)Q * ncells + 4 * ncells;  // x, r, 2 d, S32
+  else  // x, r, 2 x (BF16 n + FP32 Phi), S32
+    b += 8 * (int64_t)Q * ncells + 4 * (int64_t)Q * ncells + 2 * (2 * (int64_t)Q * ncells + 4 + 4 * ncells) +
+         4 * ncells;
   return b;
 }
 
@@ -403,7 +428,7 @@ lkp_status validate(const lkp_problem_desc *d, LatticeConstants *lc, double *tau
   if (d->order > T.max_order)
     return fail(LKP_ERR_LATTICE_ORDER, "lattice supports order <= %d (got %d)", T.max_order,
                 d->order);
-  if (d->precision < LKP_F64 || d->precision > LKP_F32_IR)
+  if (d->precision < LKP_F64 || d->precision > LKP_BF16DEV_IR)
     return fail(LKP_ERR_ARG, "unknown precision %d", d->precision);
   int64_t cells = 1;
   for (int a = 0; a < 3; ++a) {
@@ -575,7 +600,7 @@ lkp_status upload_coefficients(lkp_handle *h) {
     h->c32[i] = (float)h->c64[i];
     h->c32[Q + i] = (float)h->chi[i];
   }
-  if (h->precision == LKP_F32_IR && !h->scalar) {
+  if (h->refined() && !h->scalar) {
     HIP_TRY(hipMalloc(&h->phi_dev, Q * sizeof(double)));
     HIP_TRY(hipMemcpy(h->phi_dev, h->phi.data(), Q * sizeof(double), hipMemcpyHostToDevice));
   }
@@ -584,12 +609,32 @@ lkp_status upload_coefficients(lkp_handle *h) {
 
 void release(lkp_handle *h) {
   drop_graphs(h);
-  void *ptrs[] = {h->f[0], h->f[1], h->S, h->S32, h->phi_dev, h->r32, h->d32[0],
-                  h->d32[1], h->phib[0], h->phib[1], h->partials, h->norms_dev};
+  void *ptrs[] = {h->f[0],    h->f[1],    h->S,       h->S32,     h->phi_dev,
+                  h->r32,     h->d32[0],  h->d32[1],  h->dn[0],   h->dn[1],
+                  h->dphi[0], h->dphi[1], h->phib[0], h->phib[1], h->partials,
+                  h->norms_dev};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   if (h->capture) (void)hipStreamDestroy(h->capture);
+}
+
+// Geometry and coefficients of a BF16 deviation-storage sweep (buffers unset).
+DevParams dev_params(const lkp_handle *h) {
+  DevParams p{};
+  p.om1 = (float)(1.0 - h->omega);
+  p.nx = (unsigned)h->n[0];
+  p.ny = (unsigned)h->n[1];
+  p.nz = (unsigned)h->n[2];
+  p.ncells = h->ncells;
+  p.plane = h->ncells;
+  p.simple_wrap = h->simple_wrap ? 1u : 0u;
+  p.partials = h->partials;
+  for (int i = 0; i < h->Q; ++i) {
+    p.phi[i] = (float)h->phi[i];
+    p.chi[i] = (float)h->chi[i];
+  }
+  return p;
 }
 
 StencilParams stencil_params(const lkp_handle *h) {
@@ -752,6 +797,10 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
 
   // omega = 1 exactly: run the scalar stencil form unless populations are asked for
   h->scalar = (h->omega == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP);
+  if (h->scalar && h->bf16dev())
+    return fail(LKP_ERR_UNSUPPORTED,
+                "BF16DEV_IR at tau_lb = 1: the stencil form keeps no populations (the deviation "
+                "is exactly chi_i S); set LKP_FLAG_POPULATION_SWEEP or use F32_IR");
   if (h->scalar) return create_scalar(d, h, S);
 
   // device memory
@@ -773,8 +822,16 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
     HIP_TRY(hipMalloc(&h->f[0], Q * n * 8));  // x, the FP64 refined state
     h->f[1] = nullptr;
     HIP_TRY(hipMalloc(&h->r32, Q * n * 4));
-    HIP_TRY(hipMalloc(&h->d32[0], Q * n * 4));
-    HIP_TRY(hipMalloc(&h->d32[1], Q * n * 4));
+    if (h->bf16dev()) {
+      const size_t words = (Q * n + 1) / 2;  // BF16 planes, cleared as 32-bit words
+      for (int k = 0; k < 2; ++k) {
+        HIP_TRY(hipMalloc(&h->dn[k], words * 4));
+        HIP_TRY(hipMalloc(&h->dphi[k], n * 4));
+      }
+    } else {
+      HIP_TRY(hipMalloc(&h->d32[0], Q * n * 4));
+      HIP_TRY(hipMalloc(&h->d32[1], Q * n * 4));
+    }
     HIP_TRY(hipMalloc(&h->S, n * 8));
     HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
     std::vector<float> S32(n);
@@ -805,7 +862,8 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   HIP_TRY(launch_fill_f64(h->phib[0], 0.0, n, h->stream));
   HIP_TRY(launch_fill_f64(h->phib[1], 0.0, n, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
-  h->split = default_split(h->Q, h->precision == LKP_F32_IR ? MODE_INNER : h->mode());
+  h->split = h->bf16dev() ? dev_split(h->lattice)
+                          : default_split(h->Q, h->precision == LKP_F32_IR ? MODE_INNER : h->mode());
   return LKP_OK;
 }
 
@@ -856,8 +914,31 @@ lkp_status lkp_destroy(lkp_handle *h) {
 lkp_status lkp_step(lkp_handle *h, int64_t sweeps) {
   if (!h || sweeps < 0) return fail(LKP_ERR_ARG, "lkp_step: bad arguments");
   if (sweeps == 0) return LKP_OK;
-  if (h->precision == LKP_F32_IR)
-    return fail(LKP_ERR_UNSUPPORTED, "lkp_step drives the plain sweep; F32_IR handles use lkp_solve");
+  if (h->bf16dev()) {  // plain sweeps with BF16 deviation storage, no refinement
+    if (h->group) return fail(LKP_ERR_STATE, "lkp_step: the handle is resident in a group");
+    if (!h->dev_plain) {  // start from rest
+      const size_t QN = (size_t)h->Q * h->ncells;
+      HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(h->dn[0]), 0u, (QN + 1) / 2, h->stream));
+      HIP_TRY(launch_fill_f32(h->dphi[0], 0.0f, h->ncells, h->stream));
+      h->dev_cur = 0;
+      h->dev_plain = true;
+    }
+    for (int64_t j = 0; j < sweeps; ++j) {
+      DevParams p = dev_params(h);
+      p.nin = h->dn[h->dev_cur];
+      p.nout = h->dn[1 - h->dev_cur];
+      p.phin = h->dphi[h->dev_cur];
+      p.phout = h->dphi[1 - h->dev_cur];
+      p.src = h->S32;
+      hipError_t e = launch_dev(h->lattice, false, 0, p, h->stream);
+      if (e != hipSuccess) return fail(LKP_ERR_HIP, "deviation sweep launch: %s", hipGetErrorString(e));
+      h->dev_cur = 1 - h->dev_cur;
+    }
+    h->total_sweeps += sweeps;
+    return LKP_OK;
+  }
+  if (h->refined())
+    return fail(LKP_ERR_UNSUPPORTED, "lkp_step drives the plain sweep; refinement handles use lkp_solve");
   if (h->group) return fail(LKP_ERR_STATE, "lkp_step: the handle is resident in a group");
   if (h->scalar) {
     int cur = h->cur;
@@ -902,8 +983,9 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
   if (lkp_status st = tune_split(h)) return st;
   h->trk = Tracker();
 
-  if (h->precision == LKP_F32_IR) {
-    if (!(o->tol_rel_l2 > 0)) return fail(LKP_ERR_ARG, "F32_IR needs tol_rel_l2");
+  if (h->refined()) {
+    if (!(o->tol_rel_l2 > 0)) return fail(LKP_ERR_ARG, "refinement (F32_IR, BF16DEV_IR) needs tol_rel_l2");
+    h->dev_plain = false;
     // a resumed solve starts a fresh refinement from the current x
     h->ir = IrState();
     const int K = std::max(2, o->check_every);
@@ -936,6 +1018,27 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
         }
         h->total_sweeps += K;
         if (lkp_status st = finish_norms(h, scalar_blocks(h), h->norms_dev, h->stream)) return st;
+        if (lkp_status st = read_back(h, nr)) return st;
+        result = ir_after_inner(h, nr, K, *o, &rep);
+        if (result) break;
+        continue;
+      }
+      if (h->bf16dev()) {  // BF16 deviation-storage inner sweeps
+        for (int j = 0; j < K; ++j) {
+          DevParams p = dev_params(h);
+          p.nin = h->dn[h->ir.dc];
+          p.nout = h->dn[1 - h->ir.dc];
+          p.phin = h->dphi[h->ir.dc];
+          p.phout = h->dphi[1 - h->ir.dc];
+          const bool inner = h->ir.outer > 0;
+          p.src = inner ? h->r32 : h->S32;
+          hipError_t e = launch_dev(h->lattice, inner, j == K - 1 ? FLAG_REDUCE : 0, p, h->stream);
+          if (e != hipSuccess) return fail(LKP_ERR_HIP, "deviation sweep launch: %s", hipGetErrorString(e));
+          h->ir.dc = 1 - h->ir.dc;
+        }
+        h->total_sweeps += K;
+        if (lkp_status st = finish_norms(h, dev_blocks(h->lattice, h->ncells), h->norms_dev, h->stream))
+          return st;
         if (lkp_status st = read_back(h, nr)) return st;
         result = ir_after_inner(h, nr, K, *o, &rep);
         if (result) break;
@@ -986,7 +1089,7 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
   rep.wall_s = now_s() - t_start;
   rep.sweeps = h->total_sweeps - start;
   rep.total_sweeps = h->total_sweeps;
-  rep.outer = h->precision == LKP_F32_IR ? h->ir.outer : 0;
+  rep.outer = h->refined() ? h->ir.outer : 0;
   rep.glups = rep.wall_s > 0 ? 1e-9 * (double)h->ncells * (double)rep.sweeps / rep.wall_s : 0;
   rep.status = result;
   if (rep_out) *rep_out = rep;
@@ -1025,7 +1128,7 @@ lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r) {
     return fail(LKP_ERR_STATE, "lkp_residual needs the Phi of the last sweep (run a sweep first)");
   const int scratch = 1 - last;
   double nr[NUM_NORMS];
-  if (h->precision == LKP_F64 || h->precision == LKP_F32_IR) {
+  if (h->precision == LKP_F64 || h->refined()) {
     // FP64 residual of the FP64 state; r goes to idle storage
     const int P = default_split(h->Q, MODE_RESID);
     SweepParams p = base_params(h);
@@ -1075,6 +1178,20 @@ lkp_status lkp_get_phi(lkp_handle *h, double *dst, int32_t dst_is_device) {
                              h->stream));
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return LKP_OK;
+  }
+  if (h->dev_plain) {  // Phi of the plain deviation sweeps (FP32 storage)
+    const size_t n = h->ncells;
+    double *tmp = dst;
+    if (!dst_is_device) HIP_TRY(hipMalloc(&tmp, n * 8));
+    HIP_TRY(launch_f32_to_f64(h->dphi[h->dev_cur], tmp, n, h->stream));
+    if (!dst_is_device) {
+      HIP_TRY(hipMemcpyAsync(dst, tmp, n * 8, hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      HIP_TRY(hipFree(tmp));
+    } else {
+      HIP_TRY(hipStreamSynchronize(h->stream));
+    }
     return LKP_OK;
   }
   const int last = h->phi_last;

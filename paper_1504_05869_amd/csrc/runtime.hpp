@@ -87,6 +87,11 @@ struct lkp_handle {
   double *phi_dev = nullptr;  // phi_i on the device (IR mass projection)
   float *r32 = nullptr;
   float *d32[2] = {nullptr, nullptr};
+  // BF16DEV_IR: the correction as phi_i Phi + n_i (n_i BF16 planes, Phi FP32)
+  uint16_t *dn[2] = {nullptr, nullptr};
+  float *dphi[2] = {nullptr, nullptr};
+  int dev_cur = 0;          // current (dn, dphi) of plain deviation sweeps (lkp_step)
+  bool dev_plain = false;   // Phi comes from plain deviation sweeps (lkp_step since the last solve)
   double *phib[2] = {nullptr, nullptr};
   int64_t phi_sweep[2] = {-1, -1};
   int phi_last = 1;
@@ -113,6 +118,9 @@ struct lkp_handle {
   int64_t g_sweeps = 0;
 
   int mode() const { return precision == LKP_F64 ? lkp::MODE_F64 : lkp::MODE_F32; }
+  // FP64 refinement of the population state (FP32 or BF16-deviation inner sweeps)
+  bool refined() const { return precision == LKP_F32_IR || precision == LKP_BF16DEV_IR; }
+  bool bf16dev() const { return precision == LKP_BF16DEV_IR; }
 };
 
 namespace lkp {
