@@ -38,6 +38,10 @@ def bytes_per_cell(Q: int, precision: str) -> int:
     return 2 * b * Q + b
 
 
+def r_q(lkp, lattice: str) -> int:
+    return int(lkp.lattice_info(lattice)["Q"])
+
+
 def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=None,
                sweeps=200, chunks=1, population_sweep=False):
     """Average duration of one sweep (HIP events on the solver's stream)."""
@@ -235,6 +239,14 @@ def main():
         for prec in ("f32", "f64"):
             extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
                                           sweeps=40, population_sweep=True), grid="256^3"))
+        # BF16 deviation storage (ablation): plain deviation sweeps on the
+        # headline problem; bytes = n_i read + write (BF16), Phi read + write
+        # and S (FP32)
+        r = sweep_rate(lkp, torch, s, lattice, order, "bf16dev_ir", knudsen=kn, sweeps=200)
+        bpc_dev = 4 * r_q(lkp, lattice) + 12
+        r.update(form="BF16 deviation storage", gbs=n * bpc_dev / (r["ms_per_sweep"] * 1e-3) / 1e9)
+        r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
+        extras.append(r)
         # tau_lb = 1: the stencil form (state Phi, 3 values moved per cell)
         for prec in ("f32", "f64"):
             r = sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0, sweeps=200)
@@ -264,7 +276,8 @@ def main():
     if not args.no_extras and not args.no_tts:
         # time-to-solution on the headline problem, FP64 and FP32 + refinement
         tts = []
-        for prec, tol in (("f64", 1e-10), ("f32_ir", 1e-10), ("f32_ir", 1e-6)):
+        for prec, tol in (("f64", 1e-10), ("f32_ir", 1e-10), ("bf16dev_ir", 1e-10),
+                          ("f64", 1e-6), ("f32_ir", 1e-6), ("bf16dev_ir", 1e-6)):
             with lkp.Problem(s, lattice, order, knudsen=kn, precision=prec) as q:
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()

@@ -268,3 +268,21 @@ def test_full_size_config2_d2q81_fp64():
     e_phi, e_pop, _ = k_sweep_case("D2Q81", shape, tau, 3)
     say("full size k-sweep", e_phi, e_pop)
     assert e_phi <= 1e-13 and e_pop <= 1e-13
+
+
+@pytest.mark.parametrize("precision", ["f32_ir", "bf16dev_ir"])
+def test_full_size_config2_refinement_precisions(precision):
+    """The headline problem (1024^2, D2Q81, N = 5, Kn = 0.1) solved to
+    estimated rel-L2 1e-10 with FP32 and BF16-deviation inner sweeps: the
+    error against the exact spectral fixed point meets the FP64 bar."""
+    shape = (1024, 1024)
+    s = W.poisson_source("blobs2d", shape, seed=12345)
+    tau = OL.tau_from_knudsen(0.1, OL.get("D2Q81"), 1024)
+    with lkp.Problem(s, "D2Q81", 5, knudsen=0.1, precision=precision) as p:
+        rep = p.solve(tol_rel_l2=1e-10, check_every=100, max_sweeps=200000)
+        phi = p.phi_host()
+    ref = SP.fixed_point("D2Q81", 5, tau, s)
+    err = rel_l2(phi, ref)
+    say("full size", precision, "sweeps", rep["sweeps"], "outer", rep["outer"],
+        "est", rep["est_rel_err"], "true err", err)
+    assert err <= 1e-9
