@@ -87,6 +87,14 @@ typedef enum lkp_precision {
  * fewer bytes); populations are rebuilt on request and cannot be set.  This
  * flag keeps the population sweep instead. */
 #define LKP_FLAG_POPULATION_SWEEP 1
+/* One population buffer swept in place (F64, F32; for F32_IR the inner
+ * corrections): consecutive sweeps alternate between two storage layouts of
+ * the same buffer (a sweep that gathers from and scatters to neighbours, then
+ * one that reads and writes its own cell), which halves the population
+ * memory.  Phi and the convergence history are bitwise those of the
+ * two-buffer sweep.  Populations and the residual stay available; the
+ * velocity-group split is not tuned; such handles cannot join a group. */
+#define LKP_FLAG_IN_PLACE 2
 
 typedef struct lkp_problem_desc {
   int32_t dim;              /* 1, 2 or 3; must equal the lattice's dimension */
@@ -198,7 +206,7 @@ lkp_status lkp_lattice_info(int32_t lattice, int32_t order, int32_t *Q, int32_t 
 typedef struct lkp_handle_info {
   int32_t lattice, order, dim, Q, precision, velocity_groups;
   int32_t scalar_stencil;   /* 1: omega = 1 stencil form (state is Phi) */
-  int32_t reserved;
+  int32_t in_place;         /* 1: one population buffer swept in place (LKP_FLAG_IN_PLACE) */
   int64_t n[3];
   double tau_lb, omega, cs2;
   int64_t total_sweeps;

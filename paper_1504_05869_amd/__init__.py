@@ -57,9 +57,11 @@ def _desc(shape, lattice, order, tau_lb, knudsen, precision, subtract_mean, allo
     return d
 
 
-def footprint_bytes(shape, lattice, order, tau_lb=None, knudsen=None, precision="f64") -> int:
+def footprint_bytes(shape, lattice, order, tau_lb=None, knudsen=None, precision="f64",
+                    in_place=False) -> int:
     """Device bytes a problem of this description allocates (0 if invalid)."""
     d = _desc(shape, lattice, order, tau_lb, knudsen, precision, False, True)
+    d.flags = _lib.FLAG_IN_PLACE if in_place else 0
     return int(_lib.load().lkp_footprint_bytes(ctypes.byref(d)))
 
 
@@ -96,7 +98,8 @@ class Problem:
 
     def __init__(self, source, lattice: str, order: int, tau_lb=None, knudsen=None,
                  precision: str = "f64", subtract_mean: bool = False,
-                 allow_unstable: bool = False, stream=None, population_sweep: bool = False):
+                 allow_unstable: bool = False, stream=None, population_sweep: bool = False,
+                 in_place: bool = False):
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         if isinstance(source, torch.Tensor):
@@ -114,7 +117,8 @@ class Problem:
                   allow_unstable)
         d.source = ptr
         d.source_on_device = int(on_dev)
-        d.flags = _lib.FLAG_POPULATION_SWEEP if population_sweep else 0
+        d.flags = ((_lib.FLAG_POPULATION_SWEEP if population_sweep else 0)
+                   | (_lib.FLAG_IN_PLACE if in_place else 0))
         self._stream = _stream_handle(stream)
         d.stream = self._stream
         self.lattice, self.order, self.precision = lattice, int(order), precision

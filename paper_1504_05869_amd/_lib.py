@@ -24,6 +24,7 @@ EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_solve", "lkp
            "lkp_group_destroy"]
 MEMBER_STATES = {0: "running", 1: "converged", 2: "failed"}
 FLAG_POPULATION_SWEEP = 1
+FLAG_IN_PLACE = 2
 
 
 class ProblemDesc(ctypes.Structure):
@@ -62,7 +63,7 @@ class HandleInfo(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("order", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("Q", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("velocity_groups", ctypes.c_int32), ("scalar_stencil", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("in_place", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
                 ("tau_lb", ctypes.c_double), ("omega", ctypes.c_double),
                 ("cs2", ctypes.c_double), ("total_sweeps", ctypes.c_int64),
                 ("footprint_bytes", ctypes.c_int64)]

@@ -156,7 +156,7 @@ bool sweep_variant_available(int lattice, int mode, int P);
 
 // Per-lattice entry points, one translation unit each (sweep_<lattice>.hip).
 template <int LID>
-hipError_t launch_lattice_tu(int mode, int P, int flags, SweepParams p, hipStream_t s);
+hipError_t launch_lattice_tu(int mode, int P, int aa, int flags, SweepParams p, hipStream_t s);
 
 template <int LID>
 hipError_t launch_batch_tu(int mode, int P, int flags, const void *bp, hipStream_t s);
@@ -165,9 +165,11 @@ hipError_t launch_batch_tu(int mode, int P, int flags, const void *bp, hipStream
 // nmembers, nblocks and every member's block_begin / nblocks filled).
 hipError_t launch_sweep_batch(int lattice, int mode, int P, int flags, const void *bp, hipStream_t s);
 
-// Enqueue one sweep; fills p.nblocks.  Returns hipErrorInvalidValue for an
-// unbuilt variant.
-hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, hipStream_t s);
+// Enqueue one sweep; fills p.nblocks.  aa is the storage layout of the input
+// state: 0 pull (two buffers), 1 swapped, 2 pushed (in place, single buffer;
+// see sweep_block).  Returns hipErrorInvalidValue for an unbuilt variant.
+hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, hipStream_t s,
+                        int aa = 0);
 
 // Deterministic finish of per-block partials into out[NUM_NORMS] (device).
 hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, hipStream_t s);
@@ -178,11 +180,15 @@ hipError_t launch_f32_to_f64(const float *in, double *out, size_t n, hipStream_t
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
 // partials[NUM_NORMS * blocks] (blocks <= max_blocks, the buffer's capacity):
-// slot NORM_SUM_PHI gets the sum of d over all n values.
+// slot NORM_SUM_PHI gets the sum of d over all n values, taken in the pull
+// order (with opp non-null, d is in the swapped layout with planes of `plane`
+// values and is read through opp, so the sum rounds as for the pull layout).
 hipError_t launch_sum_f32(const float *d, size_t n, double *partials, unsigned max_blocks,
-                          unsigned *nblocks_out, hipStream_t s);
-// x_i(c) += d_i(c) - phi_i * mean, mean = sums[NORM_SUM_PHI] / ncells  (mass-mode projection)
+                          unsigned *nblocks_out, hipStream_t s, const int *opp = nullptr,
+                          unsigned plane = 0);
+// x_i(c) += d_i(c) - phi_i * mean, mean = sums[NORM_SUM_PHI] / ncells  (mass-mode projection).
+// opp (device, Q entries) non-null: d is in the swapped layout, d_i(c) at plane opp[i].
 hipError_t launch_ir_update(double *x, const float *d, const double *phi, const double *sums,
-                            unsigned Q, unsigned ncells, hipStream_t s);
+                            unsigned Q, unsigned ncells, hipStream_t s, const int *opp = nullptr);
 
 }  // namespace lkp

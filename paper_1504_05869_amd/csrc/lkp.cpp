@@ -309,10 +309,12 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
     LKP_HIP_TRY(launch_ir_update_dev((double *)h->f[0], h->dn[s.dc], h->dphi[s.dc], h->phi_dev,
                                      h->norms_dev, (unsigned)q, h->ncells, h->stream));
   } else {
-    LKP_HIP_TRY(launch_sum_f32(h->d32[s.dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream));
+    LKP_HIP_TRY(launch_sum_f32(h->d32[s.dc], QN, h->partials, (unsigned)h->partial_cap, &nb, h->stream,
+                               h->inplace ? h->opp_dev : nullptr, h->ncells));
     LKP_HIP_TRY(launch_finish(h->partials, nb, h->norms_dev, h->stream));
+    // in place the corrections sit in the swapped layout (even chunks: dc == 0)
     LKP_HIP_TRY(launch_ir_update((double *)h->f[0], h->d32[s.dc], h->phi_dev, h->norms_dev, q,
-                                 h->ncells, h->stream));
+                                 h->ncells, h->stream, h->inplace ? h->opp_dev : nullptr));
   }
   s.outer += 1;
   s.corr_prev = s.corr;
@@ -351,7 +353,8 @@ lkp_status tune_split(lkp_handle *h) {
     }
   }
   const char *off = std::getenv("LKP_AUTOTUNE");
-  if ((off && std::atoi(off) == 0) || h->ncells < 4096 || h->precision == LKP_F32_IR) {
+  // in place, a timing sweep would change the state: no tuning
+  if ((off && std::atoi(off) == 0) || h->ncells < 4096 || h->precision == LKP_F32_IR || h->inplace) {
     h->split = default_split(h->Q, mode);
     return LKP_OK;
   }
@@ -403,13 +406,14 @@ lkp_status tune_split(lkp_handle *h) {
 
 namespace {
 
-int64_t footprint_of(int precision, int Q, int64_t ncells) {
+int64_t footprint_of(int precision, int Q, int64_t ncells, bool inplace = false) {
   const int64_t nb = (ncells + 63) / 64 + 8;
+  const int64_t bufs = inplace ? 1 : 2;  // population (or correction) buffers
   int64_t b = 3 * 8 * ncells + nb * NUM_NORMS * 8 + 4096;  // S + 2 Phi + partials + misc
-  if (precision == LKP_F64) b += 2 * 8 * (int64_t)Q * ncells;
-  else if (precision == LKP_F32) b += 2 * 4 * (int64_t)Q * ncells;
-  else if (precision == LKP_F32_IR)
-    b += 8 * (int64_t)Q * ncells + 3 * 4 * (int64_t)Q * ncells + 4 * ncells;  // x, r, 2 d, S32
+  if (precision == LKP_F64) b += bufs * 8 * (int64_t)Q * ncells;
+  else if (precision == LKP_F32) b += bufs * 4 * (int64_t)Q * ncells;
+  else if (precision == LKP_F32_IR)  // x, r, d, S32
+    b += 8 * (int64_t)Q * ncells + (1 + bufs) * 4 * (int64_t)Q * ncells + 4 * ncells;
   else  // x, r, 2 x (BF16 n + FP32 Phi), S32
     b += 8 * (int64_t)Q * ncells + 4 * (int64_t)Q * ncells + 2 * (2 * (int64_t)Q * ncells + 4 + 4 * ncells) +
          4 * ncells;
@@ -466,17 +470,20 @@ lkp_status ensure_partials(lkp_handle *h, size_t nblocks) {
 
 // One population sweep of the handle's own state (F64 / F32) from buffer
 // `in` to buffer `out` with `flags`.
+// In place, buffer index `in` is the layout phase: 0 = swapped, 1 = pushed.
+int aa_of(const lkp_handle *h, int in) { return h->inplace ? (in == 0 ? 1 : 2) : 0; }
+
 lkp_status enqueue_sweep(lkp_handle *h, hipStream_t s, int in, int out, int flags,
-                         const double *phi_prev, double *phi_out) {
+                         const double *phi_prev, double *phi_out, bool dry = false) {
   SweepParams p = base_params(h);
   p.fin = h->f[in];
-  p.fout = h->f[out];
+  p.fout = dry ? nullptr : h->f[out];
   p.src = h->S;
   set_coefficients(h, h->mode(), &p);
   p.phi_prev = phi_prev;
   p.phi_out = phi_out;
   p.partials = h->partials;
-  hipError_t e = launch_sweep(h->lattice, h->mode(), h->split, flags, p, s);
+  hipError_t e = launch_sweep(h->lattice, h->mode(), h->split, flags, p, s, aa_of(h, in));
   if (e != hipSuccess) return fail(LKP_ERR_HIP, "sweep launch: %s", hipGetErrorString(e));
   return LKP_OK;
 }
@@ -613,8 +620,12 @@ void release(lkp_handle *h) {
                   h->r32,     h->d32[0],  h->d32[1],  h->dn[0],   h->dn[1],
                   h->dphi[0], h->dphi[1], h->phib[0], h->phib[1], h->partials,
                   h->norms_dev};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  for (size_t k = 0; k < sizeof ptrs / sizeof ptrs[0]; ++k) {  // in place, two slots share a buffer
+    bool seen = false;
+    for (size_t j = 0; j < k; ++j) seen = seen || ptrs[j] == ptrs[k];
+    if (ptrs[k] && !seen) (void)hipFree(ptrs[k]);
+  }
+  if (h->opp_dev) (void)hipFree(h->opp_dev);
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   if (h->capture) (void)hipStreamDestroy(h->capture);
 }
@@ -802,18 +813,23 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
                 "BF16DEV_IR at tau_lb = 1: the stencil form keeps no populations (the deviation "
                 "is exactly chi_i S); set LKP_FLAG_POPULATION_SWEEP or use F32_IR");
   if (h->scalar) return create_scalar(d, h, S);
+  h->inplace = (d->flags & LKP_FLAG_IN_PLACE) != 0;
+  if (h->inplace && h->bf16dev())
+    return fail(LKP_ERR_UNSUPPORTED, "LKP_FLAG_IN_PLACE is not available for BF16DEV_IR");
 
   // device memory
   const size_t Q = h->Q;
-  h->footprint = footprint_of(h->precision, h->Q, h->ncells);
+  h->footprint = footprint_of(h->precision, h->Q, h->ncells, h->inplace);
   if (h->precision == LKP_F64) {
     HIP_TRY(hipMalloc(&h->f[0], Q * n * 8));
-    HIP_TRY(hipMalloc(&h->f[1], Q * n * 8));
+    if (h->inplace) h->f[1] = h->f[0];
+    else HIP_TRY(hipMalloc(&h->f[1], Q * n * 8));
     HIP_TRY(hipMalloc(&h->S, n * 8));
     HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
   } else if (h->precision == LKP_F32) {
     HIP_TRY(hipMalloc(&h->f[0], Q * n * 4));
-    HIP_TRY(hipMalloc(&h->f[1], Q * n * 4));
+    if (h->inplace) h->f[1] = h->f[0];
+    else HIP_TRY(hipMalloc(&h->f[1], Q * n * 4));
     std::vector<float> S32(n);
     for (size_t c = 0; c < n; ++c) S32[c] = (float)S[c];
     HIP_TRY(hipMalloc(&h->S, n * 4));
@@ -830,7 +846,18 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
       }
     } else {
       HIP_TRY(hipMalloc(&h->d32[0], Q * n * 4));
-      HIP_TRY(hipMalloc(&h->d32[1], Q * n * 4));
+      if (h->inplace) {
+        h->d32[1] = h->d32[0];
+        const VelTable T = velocity_table(h->lattice);
+        const VelMaps M = build_maps(T);
+        std::vector<int> opp(Q);
+        for (size_t i = 0; i < Q; ++i)
+          opp[i] = M.vidx[6 - T.v[i][0]][6 - T.v[i][1]][6 - T.v[i][2]];
+        HIP_TRY(hipMalloc(&h->opp_dev, Q * sizeof(int)));
+        HIP_TRY(hipMemcpy(h->opp_dev, opp.data(), Q * sizeof(int), hipMemcpyHostToDevice));
+      } else {
+        HIP_TRY(hipMalloc(&h->d32[1], Q * n * 4));
+      }
     }
     HIP_TRY(hipMalloc(&h->S, n * 8));
     HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
@@ -867,6 +894,43 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   return LKP_OK;
 }
 
+// In-place layouts <-> the pull layout f*_i(y) (host copies, FP64).
+//   phase 0 (swapped): f*_i(y) at plane opp(i), cell y
+//   phase 1 (pushed):  f*_i(y) at plane i, cell y + v_i
+void inplace_to_pull(const lkp_handle *h, int phase, const std::vector<double> &raw,
+                     std::vector<double> &out) {
+  const VelTable T = velocity_table(h->lattice);
+  const VelMaps M = build_maps(T);
+  const int64_t nx = h->n[0], ny = h->n[1], nz = h->n[2], n = h->ncells;
+  out.assign(raw.size(), 0.0);
+  for (int i = 0; i < h->Q; ++i) {
+    const int oi = M.vidx[6 - T.v[i][0]][6 - T.v[i][1]][6 - T.v[i][2]];
+    for (int64_t z = 0; z < nz; ++z)
+      for (int64_t y = 0; y < ny; ++y)
+        for (int64_t x = 0; x < nx; ++x) {
+          const int64_t c = (z * ny + y) * nx + x;
+          if (phase == 0) {
+            out[(size_t)i * n + c] = raw[(size_t)oi * n + c];
+          } else {
+            const int64_t xs = ((x + T.v[i][0]) % nx + nx) % nx, ys = ((y + T.v[i][1]) % ny + ny) % ny,
+                          zs = ((z + T.v[i][2]) % nz + nz) % nz;
+            out[(size_t)i * n + c] = raw[(size_t)i * n + (zs * ny + ys) * nx + xs];
+          }
+        }
+  }
+}
+
+void pull_to_swapped(const lkp_handle *h, const std::vector<double> &in, std::vector<double> &raw) {
+  const VelTable T = velocity_table(h->lattice);
+  const VelMaps M = build_maps(T);
+  const size_t n = h->ncells;
+  raw.assign(in.size(), 0.0);
+  for (int i = 0; i < h->Q; ++i) {
+    const int oi = M.vidx[6 - T.v[i][0]][6 - T.v[i][1]][6 - T.v[i][2]];
+    std::memcpy(&raw[(size_t)oi * n], &in[(size_t)i * n], n * sizeof(double));
+  }
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -883,7 +947,9 @@ int64_t lkp_footprint_bytes(const lkp_problem_desc *d) {
     lkp::rt::fail(LKP_OK, "%s", keep.c_str());
     return 0;
   }
-  return footprint_of(d->precision, lc.table.q, d->n[0] * d->n[1] * d->n[2]);
+  const bool scalar = (1.0 / tau == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP);
+  return footprint_of(d->precision, lc.table.q, d->n[0] * d->n[1] * d->n[2],
+                      (d->flags & LKP_FLAG_IN_PLACE) && !scalar);
 }
 
 lkp_status lkp_create(const lkp_problem_desc *d, lkp_handle **out) {
@@ -988,7 +1054,8 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
     h->dev_plain = false;
     // a resumed solve starts a fresh refinement from the current x
     h->ir = IrState();
-    const int K = std::max(2, o->check_every);
+    int K = std::max(2, o->check_every);
+    if (h->inplace) K += K & 1;  // corrections end each chunk in the swapped layout
     bool converged = false;
     while (!converged) {
       double nr[NUM_NORMS];
@@ -1049,7 +1116,8 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
         int flags = 0;
         if (j == K - 2) { flags = FLAG_PHI; p.phi_out = h->phib[0]; }
         if (j == K - 1) { flags = FLAG_REDUCE; p.phi_prev = h->phib[0]; p.phi_out = h->phib[1]; }
-        hipError_t e = launch_sweep(h->lattice, ir_inner_mode(h), P, flags, p, h->stream);
+        hipError_t e = launch_sweep(h->lattice, ir_inner_mode(h), P, flags, p, h->stream,
+                                    aa_of(h, h->ir.dc));
         if (e != hipSuccess) return fail(LKP_ERR_HIP, "inner sweep launch: %s", hipGetErrorString(e));
         h->ir.dc = 1 - h->ir.dc;
       }
@@ -1132,20 +1200,23 @@ lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r) {
     // FP64 residual of the FP64 state; r goes to idle storage
     const int P = default_split(h->Q, MODE_RESID);
     SweepParams p = base_params(h);
-    p.fin = h->precision == LKP_F64 ? h->f[h->cur] : h->f[0];
-    p.fout = h->precision == LKP_F64 ? h->f[1 - h->cur] : (void *)h->r32;
+    const bool f64 = h->precision == LKP_F64;
+    p.fin = f64 ? h->f[h->cur] : h->f[0];
+    // r goes to the idle buffer; in place there is none and only the norms are kept
+    p.fout = f64 ? (h->inplace ? nullptr : h->f[1 - h->cur]) : (void *)h->r32;
     p.src = h->S;
     set_coefficients(h, MODE_RESID, &p);
     p.phi_prev = h->phib[last];
     p.phi_out = h->phib[scratch];
     p.partials = h->partials;
-    hipError_t e = launch_sweep(h->lattice, MODE_RESID, P, FLAG_REDUCE, p, h->stream);
+    hipError_t e = launch_sweep(h->lattice, MODE_RESID, P, FLAG_REDUCE, p, h->stream,
+                                f64 ? aa_of(h, h->cur) : 0);
     if (e != hipSuccess) return fail(LKP_ERR_HIP, "residual launch: %s", hipGetErrorString(e));
     if (lkp_status st = read_norms(h, sweep_blocks(h, P), nr)) return st;
     r->pop_residual_l2 = std::sqrt(nr[NORM_SUM_R2]);
   } else {
     if (lkp_status st = enqueue_sweep(h, h->stream, h->cur, 1 - h->cur, FLAG_REDUCE, h->phib[last],
-                                      h->phib[scratch]))
+                                      h->phib[scratch], h->inplace))
       return st;
     if (lkp_status st = read_norms(h, sweep_blocks(h, h->split), nr)) return st;
     r->pop_residual_l2 = NAN;
@@ -1218,6 +1289,19 @@ lkp_status lkp_get_populations(lkp_handle *h, double *dst, int32_t dst_is_device
     return LKP_OK;
   }
   const size_t QN = (size_t)h->Q * h->ncells;
+  if (h->inplace && !h->refined()) {  // one buffer in one of two layouts: remap to the pull layout
+    std::vector<double> raw(QN), out;
+    double *tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, QN * 8));
+    if (h->precision == LKP_F32) HIP_TRY(launch_f32_to_f64((const float *)h->f[0], tmp, QN, h->stream));
+    else HIP_TRY(hipMemcpyAsync(tmp, h->f[0], QN * 8, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(raw.data(), tmp, QN * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipFree(tmp));
+    inplace_to_pull(h, h->cur, raw, out);
+    HIP_TRY(hipMemcpy(dst, out.data(), QN * 8, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    return LKP_OK;
+  }
   if (h->precision == LKP_F32) {
     double *tmp = dst;
     if (!dst_is_device) HIP_TRY(hipMalloc(&tmp, QN * 8));
@@ -1243,6 +1327,21 @@ lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_
     return fail(LKP_ERR_UNSUPPORTED, "the tau_lb = 1 stencil form keeps Phi only; create the handle "
                                      "with LKP_FLAG_POPULATION_SWEEP to set populations");
   const size_t QN = (size_t)h->Q * h->ncells;
+  if (h->inplace && !h->refined()) {  // store in the swapped layout (phase 0)
+    std::vector<double> in(QN), raw;
+    HIP_TRY(hipMemcpy(in.data(), src, QN * 8, src_is_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    pull_to_swapped(h, in, raw);
+    double *tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, QN * 8));
+    HIP_TRY(hipMemcpyAsync(tmp, raw.data(), QN * 8, hipMemcpyHostToDevice, h->stream));
+    if (h->precision == LKP_F32) HIP_TRY(launch_f64_to_f32(tmp, (float *)h->f[0], QN, h->stream));
+    else HIP_TRY(hipMemcpyAsync(h->f[0], tmp, QN * 8, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipFree(tmp));
+    h->cur = 0;
+    h->phi_sweep[0] = h->phi_sweep[1] = -1;
+    return LKP_OK;
+  }
   const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (h->precision == LKP_F32) {
     double *tmp = nullptr;
@@ -1291,7 +1390,7 @@ lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info) {
   info->precision = h->precision;
   info->velocity_groups = h->split;
   info->scalar_stencil = h->scalar ? 1 : 0;
-  info->reserved = 0;
+  info->in_place = h->inplace ? 1 : 0;
   for (int a = 0; a < 3; ++a) info->n[a] = h->n[a];
   info->tau_lb = h->tau_lb;
   info->omega = h->omega;

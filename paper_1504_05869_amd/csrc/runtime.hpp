@@ -90,6 +90,8 @@ struct lkp_handle {
   // BF16DEV_IR: the correction as phi_i Phi + n_i (n_i BF16 planes, Phi FP32)
   uint16_t *dn[2] = {nullptr, nullptr};
   float *dphi[2] = {nullptr, nullptr};
+  bool inplace = false;     // LKP_FLAG_IN_PLACE: f[1] == f[0] (d32[1] == d32[0] for F32_IR)
+  int *opp_dev = nullptr;   // in place + F32_IR: opposite-velocity map for the update
   int dev_cur = 0;          // current (dn, dphi) of plain deviation sweeps (lkp_step)
   bool dev_plain = false;   // Phi comes from plain deviation sweeps (lkp_step since the last solve)
   double *phib[2] = {nullptr, nullptr};

@@ -43,22 +43,29 @@ __global__ void k_fill(T *__restrict__ p, T v, size_t n) {
 }
 
 __global__ void __launch_bounds__(256) k_sum_f32(const float *__restrict__ d, size_t n,
-                                                 double *__restrict__ partials) {
+                                                 double *__restrict__ partials,
+                                                 const int *__restrict__ opp, unsigned plane) {
   double v[NUM_NORMS] = {0, 0, 0, 0, 0, 0};
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-    v[NORM_SUM_PHI] += (double)d[i];
+  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+    // swapped layout: element k of the pull order sits in plane opp[k / plane]
+    const size_t src = opp ? (size_t)opp[k / plane] * plane + k % plane : k;
+    v[NORM_SUM_PHI] += (double)d[src];
+  }
   block_norms(v, partials + (size_t)blockIdx.x * NUM_NORMS);
 }
 
 __global__ void __launch_bounds__(256) k_ir_update(double *__restrict__ x, const float *__restrict__ d,
                                                    const double *__restrict__ phi,
                                                    const double *__restrict__ sums, unsigned Q,
-                                                   unsigned ncells) {
+                                                   unsigned ncells,
+                                                   const int *__restrict__ opp) {
   const double mean = sums[NORM_SUM_PHI] / (double)ncells;
   const size_t n = (size_t)Q * ncells;
   for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
     const unsigned i = (unsigned)(k / ncells);
-    x[k] += (double)d[k] - phi[i] * mean;
+    // swapped layout (in place): d_i(c) sits in plane opp[i]
+    const size_t src = opp ? (size_t)opp[i] * ncells + (k - (size_t)i * ncells) : k;
+    x[k] += (double)d[src] - phi[i] * mean;
   }
 }
 
@@ -75,20 +82,20 @@ bool sweep_variant_available(int lattice, int mode, int P) {
   return sweep_variant_built(lattice, mode, P);
 }
 
-hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, hipStream_t s) {
+hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, hipStream_t s, int aa) {
   if (!sweep_variant_available(lattice, mode, P)) return hipErrorInvalidValue;
   const unsigned cells = cells_per_block(P);
   p.nblocks = (p.ncells + cells - 1) / cells;
   switch (lattice) {
-    case D1Q5: return launch_lattice_tu<D1Q5>(mode, P, flags, p, s);
-    case D1Q9: return launch_lattice_tu<D1Q9>(mode, P, flags, p, s);
-    case D1Q13: return launch_lattice_tu<D1Q13>(mode, P, flags, p, s);
-    case D2Q5: return launch_lattice_tu<D2Q5>(mode, P, flags, p, s);
-    case D2Q9: return launch_lattice_tu<D2Q9>(mode, P, flags, p, s);
-    case D2Q25: return launch_lattice_tu<D2Q25>(mode, P, flags, p, s);
-    case D2Q81: return launch_lattice_tu<D2Q81>(mode, P, flags, p, s);
-    case D2Q169: return launch_lattice_tu<D2Q169>(mode, P, flags, p, s);
-    case D3Q111: return launch_lattice_tu<D3Q111>(mode, P, flags, p, s);
+    case D1Q5: return launch_lattice_tu<D1Q5>(mode, P, aa, flags, p, s);
+    case D1Q9: return launch_lattice_tu<D1Q9>(mode, P, aa, flags, p, s);
+    case D1Q13: return launch_lattice_tu<D1Q13>(mode, P, aa, flags, p, s);
+    case D2Q5: return launch_lattice_tu<D2Q5>(mode, P, aa, flags, p, s);
+    case D2Q9: return launch_lattice_tu<D2Q9>(mode, P, aa, flags, p, s);
+    case D2Q25: return launch_lattice_tu<D2Q25>(mode, P, aa, flags, p, s);
+    case D2Q81: return launch_lattice_tu<D2Q81>(mode, P, aa, flags, p, s);
+    case D2Q169: return launch_lattice_tu<D2Q169>(mode, P, aa, flags, p, s);
+    case D3Q111: return launch_lattice_tu<D3Q111>(mode, P, aa, flags, p, s);
   }
   return hipErrorInvalidValue;
 }
@@ -155,19 +162,20 @@ hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s) {
 }
 
 hipError_t launch_sum_f32(const float *d, size_t n, double *partials, unsigned max_blocks,
-                          unsigned *nblocks_out, hipStream_t s) {
+                          unsigned *nblocks_out, hipStream_t s, const int *opp, unsigned plane) {
   unsigned nb = grid_for(n) > 4096 ? 4096 : grid_for(n);
   if (nb > max_blocks) nb = max_blocks;
-  if (nb == 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sum_f32, dim3(nb), dim3(256), 0, s, d, n, partials);
+  if (nb == 0 || (opp && plane == 0)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sum_f32, dim3(nb), dim3(256), 0, s, d, n, partials, opp, plane);
   *nblocks_out = nb;
   return hipGetLastError();
 }
 
 hipError_t launch_ir_update(double *x, const float *d, const double *phi, const double *sums,
-                            unsigned Q, unsigned ncells, hipStream_t s) {
+                            unsigned Q, unsigned ncells, hipStream_t s, const int *opp) {
   const size_t n = (size_t)Q * ncells;
-  hipLaunchKernelGGL(k_ir_update, dim3(grid_for(n)), dim3(256), 0, s, x, d, phi, sums, Q, ncells);
+  hipLaunchKernelGGL(k_ir_update, dim3(grid_for(n)), dim3(256), 0, s, x, d, phi, sums, Q, ncells,
+                     opp);
   return hipGetLastError();
 }
 

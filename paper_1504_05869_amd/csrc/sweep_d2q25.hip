@@ -5,7 +5,7 @@
 #include "sweep_impl.hpp"
 
 namespace lkp {
-template hipError_t launch_lattice_tu<D2Q25>(int, int, int, SweepParams, hipStream_t);
+template hipError_t launch_lattice_tu<D2Q25>(int, int, int, int, SweepParams, hipStream_t);
 template hipError_t launch_batch_tu<D2Q25>(int, int, int, const void *, hipStream_t);
 template hipError_t launch_stencil_tu<D2Q25>(int, int, const StencilParams &, hipStream_t);
 template hipError_t launch_dev_tu<D2Q25>(bool, int, DevParams, hipStream_t);

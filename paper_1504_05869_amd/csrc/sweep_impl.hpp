@@ -117,7 +117,20 @@ struct CoefScaled {  // batched launches: omega phi_i formed in FP64 exactly as 
 
 // One block's share of a sweep: cells [blk * CELLS, blk * CELLS + CELLS) of
 // the problem described by p (SweepParams or BatchMember).
-template <int LID, int MODE, int P, int FLAGS, class Params, class C>
+//
+// AA selects the storage of the input state (in-place single-buffer sweeps
+// alternate between two layouts; the values computed are those of the pull
+// sweep, in the same order):
+//   AA = 0  pull layout, two buffers: f*_i(y) at plane i, cell y.
+//   AA = 1  swapped layout: f*_i(y) at plane opp(i), cell y.  The sweep reads
+//           f*_i(x - v_i) there and writes f*'_i(x) to plane i, cell x + v_i.
+//   AA = 2  pushed layout: f*_i(y) at plane i, cell y + v_i.  The sweep reads
+//           f*_i(x - v_i) at plane i, cell x, and writes f*'_i(x) to plane
+//           opp(i), cell x: the swapped layout again.
+// Every location an AA sweep writes is read by the same cell in the same
+// sweep (and by nothing else), before the block's barrier, so the update is
+// safe in place.
+template <int LID, int MODE, int P, int FLAGS, int AA, class Params, class C>
 __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const C &coef) {
   using L = Lattice<LID>;
   using MT = ModeTraits<MODE>;
@@ -153,8 +166,9 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
   // (every plane is < 4 GiB), which maps to scalar-base + vector-offset
   // addressing.
   const size_t plane = p.plane;
-  const char *__restrict__ fin = reinterpret_cast<const char *>(p.fin);
-  char *__restrict__ fout = reinterpret_cast<char *>(p.fout);
+  // in place (AA > 0) the two point to the same buffer: no restrict
+  const char *fin = reinterpret_cast<const char *>(p.fin);
+  char *fout = reinterpret_cast<char *>(p.fout);
   const char *__restrict__ src = reinterpret_cast<const char *>(p.src);
   const unsigned c_in = cc * (unsigned)sizeof(TIN);
   const unsigned c_out = c * (unsigned)sizeof(TOUT);
@@ -169,8 +183,10 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
     static_for<lo, hi>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int vx = L::table.v[i][0], vy = L::table.v[i][1], vz = L::table.v[i][2];
-      const unsigned off = (zw[vz + VMZ] * p.ny + yw[vy + VMY]) * p.nx + xw[vx + VMX];
-      vals[i - lo] = ld<TIN>(fin + (size_t)i * plane * sizeof(TIN), off * (unsigned)sizeof(TIN));
+      static_assert(L::vel(-vx, -vy, -vz) >= 0, "in-place layouts need a symmetric velocity set");
+      constexpr int li = AA == 1 ? L::vel(-vx, -vy, -vz) : i;  // plane holding f*_i
+      const unsigned off = AA == 2 ? cc : (zw[vz + VMZ] * p.ny + yw[vy + VMY]) * p.nx + xw[vx + VMX];
+      vals[i - lo] = ld<TIN>(fin + (size_t)li * plane * sizeof(TIN), off * (unsigned)sizeof(TIN));
     });
     // moment in velocity order, FP64
     static_for<lo, hi>([&](auto I) { part += (double)vals[(int)I - lo]; });
@@ -214,14 +230,28 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
       } else {
         val = om1 * (TC)vals[i - lo] + coef.wphi(i) * phic + coef.chi(i) * sc;
       }
-      char *obase = fout + (size_t)i * plane * sizeof(TOUT);
+      constexpr int vx = L::table.v[i][0], vy = L::table.v[i][1], vz = L::table.v[i][2];
+      constexpr int oi = L::vel(-vx, -vy, -vz);
       if constexpr (MT::RESID) {
-        const double xi = (double)ld<TIN>(fin + (size_t)i * plane * sizeof(TIN), c_in);
+        // own f*_i(x) in the input layout; r is written in the pull layout
+        double xi;
+        if constexpr (AA == 2) {
+          const unsigned pushed =
+              (zw[VMZ - vz] * p.ny + yw[VMY - vy]) * p.nx + xw[VMX - vx];  // x + v_i
+          xi = (double)ld<TIN>(fin + (size_t)i * plane * sizeof(TIN), pushed * (unsigned)sizeof(TIN));
+        } else {
+          xi = (double)ld<TIN>(fin + (size_t)(AA == 1 ? oi : i) * plane * sizeof(TIN), c_in);
+        }
         const double r = (double)val - xi;
         r2 += r * r;
-        if (valid) st<TOUT>(obase, c_out, (TOUT)r);
+        if (valid && fout) st<TOUT>(fout + (size_t)i * plane * sizeof(TOUT), c_out, (TOUT)r);
+      } else if constexpr (AA == 1) {
+        const unsigned pushed = (zw[VMZ - vz] * p.ny + yw[VMY - vy]) * p.nx + xw[VMX - vx];
+        if (valid && fout)
+          st<TOUT>(fout + (size_t)i * plane * sizeof(TOUT), pushed * (unsigned)sizeof(TOUT), (TOUT)val);
       } else {
-        if (valid) st<TOUT>(obase, c_out, (TOUT)val);
+        char *obase = fout + (size_t)(AA == 2 ? oi : i) * plane * sizeof(TOUT);
+        if (valid && fout) st<TOUT>(obase, c_out, (TOUT)val);  // no fout: norms only
       }
     });
   };
@@ -270,7 +300,7 @@ __device__ __forceinline__ unsigned block_order(unsigned b, unsigned nb) {
 #endif
 }
 
-template <int LID, int MODE, int P, int FLAGS>
+template <int LID, int MODE, int P, int FLAGS, int AA>
 __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
   using TC = typename ModeTraits<MODE>::TC;
   const unsigned blk = block_order(blockIdx.x, p.nblocks);
@@ -278,7 +308,7 @@ __global__ void __launch_bounds__(256) k_sweep(SweepParams p) {
   if constexpr (sizeof(TC) == 8) coef.c = p.coef.d;
   else coef.c = p.coef.f;
   coef.q = Lattice<LID>::Q;
-  sweep_block<LID, MODE, P, FLAGS>(p, blk, coef);
+  sweep_block<LID, MODE, P, FLAGS, AA>(p, blk, coef);
 }
 
 // Many problems of one lattice class in one launch: blocks are numbered
@@ -293,25 +323,35 @@ __global__ void __launch_bounds__(256) k_sweep_batch(BatchParams<Lattice<LID>::Q
     if (bp.m[k].block_begin <= gb) j = k;
   const BatchMember &m = bp.m[j];
   CoefScaled<TC> coef{m.omega, bp.phi, bp.chi};
-  sweep_block<LID, MODE, P, FLAGS>(m, gb - m.block_begin, coef);
+  sweep_block<LID, MODE, P, FLAGS, 0>(m, gb - m.block_begin, coef);
 }
 
 
 
-template <int LID, int MODE, int P>
+template <int LID, int MODE, int P, int AA>
 hipError_t launch_flags(int flags, SweepParams p, hipStream_t s) {
   dim3 grid(p.nblocks), block(256);
   if (flags & FLAG_REDUCE)
-    hipLaunchKernelGGL((k_sweep<LID, MODE, P, FLAG_REDUCE | FLAG_PHI>), grid, block, 0, s, p);
+    hipLaunchKernelGGL((k_sweep<LID, MODE, P, FLAG_REDUCE | FLAG_PHI, AA>), grid, block, 0, s, p);
   else if constexpr (MODE != MODE_RESID) {
     if (flags & FLAG_PHI)
-      hipLaunchKernelGGL((k_sweep<LID, MODE, P, FLAG_PHI>), grid, block, 0, s, p);
+      hipLaunchKernelGGL((k_sweep<LID, MODE, P, FLAG_PHI, AA>), grid, block, 0, s, p);
     else
-      hipLaunchKernelGGL((k_sweep<LID, MODE, P, 0>), grid, block, 0, s, p);
+      hipLaunchKernelGGL((k_sweep<LID, MODE, P, 0, AA>), grid, block, 0, s, p);
   } else {
     return hipErrorInvalidValue;  // the residual sweep always reduces
   }
   return hipGetLastError();
+}
+
+template <int LID, int MODE, int P>
+hipError_t launch_aa(int aa, int flags, SweepParams p, hipStream_t s) {
+  switch (aa) {
+    case 0: return launch_flags<LID, MODE, P, 0>(flags, p, s);
+    case 1: return launch_flags<LID, MODE, P, 1>(flags, p, s);
+    case 2: return launch_flags<LID, MODE, P, 2>(flags, p, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int LID, int MODE, int P>
@@ -358,28 +398,28 @@ hipError_t launch_batch_lattice(int mode, int P, int flags, const void *bp, hipS
 }
 
 template <int LID, int MODE>
-hipError_t launch_mode(int P, int flags, SweepParams p, hipStream_t s) {
+hipError_t launch_mode(int P, int aa, int flags, SweepParams p, hipStream_t s) {
   switch (P) {
     case 1:
-      if constexpr (sweep_variant_built(LID, MODE, 1)) return launch_flags<LID, MODE, 1>(flags, p, s);
+      if constexpr (sweep_variant_built(LID, MODE, 1)) return launch_aa<LID, MODE, 1>(aa, flags, p, s);
       break;
     case 2:
-      if constexpr (sweep_variant_built(LID, MODE, 2)) return launch_flags<LID, MODE, 2>(flags, p, s);
+      if constexpr (sweep_variant_built(LID, MODE, 2)) return launch_aa<LID, MODE, 2>(aa, flags, p, s);
       break;
     case 4:
-      if constexpr (sweep_variant_built(LID, MODE, 4)) return launch_flags<LID, MODE, 4>(flags, p, s);
+      if constexpr (sweep_variant_built(LID, MODE, 4)) return launch_aa<LID, MODE, 4>(aa, flags, p, s);
       break;
   }
   return hipErrorInvalidValue;
 }
 
 template <int LID>
-hipError_t launch_lattice(int mode, int P, int flags, SweepParams p, hipStream_t s) {
+hipError_t launch_lattice(int mode, int P, int aa, int flags, SweepParams p, hipStream_t s) {
   switch (mode) {
-    case MODE_F64: return launch_mode<LID, MODE_F64>(P, flags, p, s);
-    case MODE_F32: return launch_mode<LID, MODE_F32>(P, flags, p, s);
-    case MODE_RESID: return launch_mode<LID, MODE_RESID>(P, flags, p, s);
-    case MODE_INNER: return launch_mode<LID, MODE_INNER>(P, flags, p, s);
+    case MODE_F64: return launch_mode<LID, MODE_F64>(P, aa, flags, p, s);
+    case MODE_F32: return launch_mode<LID, MODE_F32>(P, aa, flags, p, s);
+    case MODE_RESID: return launch_mode<LID, MODE_RESID>(P, aa, flags, p, s);
+    case MODE_INNER: return launch_mode<LID, MODE_INNER>(P, aa, flags, p, s);
   }
   return hipErrorInvalidValue;
 }
@@ -387,8 +427,8 @@ hipError_t launch_lattice(int mode, int P, int flags, SweepParams p, hipStream_t
 }  // namespace sweep_detail
 
 template <int LID>
-hipError_t launch_lattice_tu(int mode, int P, int flags, SweepParams p, hipStream_t s) {
-  return sweep_detail::launch_lattice<LID>(mode, P, flags, p, s);
+hipError_t launch_lattice_tu(int mode, int P, int aa, int flags, SweepParams p, hipStream_t s) {
+  return sweep_detail::launch_lattice<LID>(mode, P, aa, flags, p, s);
 }
 
 template <int LID>

@@ -120,3 +120,14 @@ def test_knudsen_mapping_matches_oracle():
     tau = OL.tau_from_knudsen(0.1, OL.get("D2Q81"), 1024)
     assert 118.0 < tau < 118.6
     assert d.knudsen == 0.1
+
+
+def test_in_place_halves_population_footprint():
+    """One population buffer instead of two (F64, F32) or one correction buffer
+    instead of two (F32_IR): 512^3 D3Q111 F32_IR then fits 288 GB."""
+    for prec, per in (("f64", 8), ("f32", 4), ("f32_ir", 4)):
+        a = lkp.footprint_bytes((64, 64, 64), "D3Q111", 5, knudsen=0.3, precision=prec)
+        b = lkp.footprint_bytes((64, 64, 64), "D3Q111", 5, knudsen=0.3, precision=prec, in_place=True)
+        assert a - b == per * 111 * 64 ** 3
+    big = lkp.footprint_bytes((512, 512, 512), "D3Q111", 5, knudsen=0.3, precision="f32_ir", in_place=True)
+    assert big < 288e9 < lkp.footprint_bytes((512, 512, 512), "D3Q111", 5, knudsen=0.3, precision="f32_ir")
