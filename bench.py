@@ -108,6 +108,52 @@ def cpu_baseline(s, lattice, order, tau, seconds=15.0):
                       f"FP64 grid in {dt:.1f} s"}
 
 
+def stiff_512(lkp, torch, tol: float, chunk: int, minutes: float) -> dict:
+    """512^3 D3Q111 N=5, Kn = 0.3 (tau_lb = 184.4), 4096 point-like Gaussians:
+    FP32 sweeps + FP64 refinement (in place: 238 GB) against the plain FP64
+    sweep (two buffers: 238 GB), each solved to estimated rel-L2 `tol`.  The
+    solve runs as consecutive lkp_solve calls of `chunk` sweeps (a refinement
+    stopped by max_sweeps keeps its partial correction and resumes from it),
+    one progress line per call on stderr.  A solve still short of `tol` after
+    `minutes` of wall time reports its reached error and the contraction rate,
+    and a time extrapolated from that rate (labelled as such)."""
+    from paper_1504_05869_amd import workloads as W
+    shape = (512, 512, 512)
+    t0 = time.perf_counter()
+    s = W.poisson_source("stiff3d", shape, seed=5120)
+    gen_s = time.perf_counter() - t0
+    out = {"workload": "512^3 D3Q111 N=5 Kn=0.3, 4096 Gaussians sigma=1, amplitudes +-U(1,10), zero mean",
+           "tol_rel_l2": tol, "source_generation_s": round(gen_s, 1), "runs": []}
+    for prec, in_place in (("f32_ir", True), ("f64", False)):
+        with lkp.Problem(s, "D3Q111", 5, knudsen=0.3, precision=prec, in_place=in_place) as q:
+            info = q.info()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sweeps, outer, rep, hist = 0, 0, None, []
+            while True:
+                rep = q.solve(tol_rel_l2=tol, check_every=200, max_sweeps=chunk, raise_on_error=False)
+                sweeps += rep["sweeps"]
+                outer += rep["outer"]
+                el = time.perf_counter() - t1
+                hist.append((el, sweeps, rep["est_rel_err"]))
+                print(f"[c5] {prec} in_place={in_place} {sweeps} sweeps {el:.0f} s est {rep['est_rel_err']:.3e} "
+                      f"status {rep['status']}", file=sys.stderr, flush=True)
+                if rep["status"] == 0 or el > 60 * minutes:
+                    break
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            run = {"precision": prec, "in_place": in_place, "footprint_gb": round(info["footprint_bytes"] / 1e9, 1),
+                   "converged": rep["status"] == 0, "seconds": round(el, 1), "sweeps": sweeps,
+                   "outer": outer, "est_rel_err": rep["est_rel_err"], "rate": rep["rate"],
+                   "ms_per_sweep": round(el / max(sweeps, 1) * 1e3, 2)}
+            if rep["status"] != 0 and 0 < rep["rate"] < 1 and rep["est_rel_err"] > tol:
+                import math
+                more = math.log(tol / rep["est_rel_err"]) / math.log(rep["rate"])
+                run["extrapolated_seconds"] = round(el + more * el / max(sweeps, 1), 1)
+            out["runs"].append(run)
+    return out
+
+
 def serving_run(n_requests: int, rate: float) -> dict:
     """Scaled serving stream: continuous batching (FP32 + refinement) against
     the same trace solved one at a time in FP64, both to estimated rel-L2 1e-6."""
@@ -142,6 +188,10 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--c5", action="store_true",
+                    help="only the 512^3 stiff workload: FP32+IR in place vs FP64 (long)")
+    ap.add_argument("--c5-tol", type=float, default=1e-10)
+    ap.add_argument("--c5-minutes", type=float, default=7.0, help="wall-time cap per solve")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -155,6 +205,10 @@ def main():
     from paper_1504_05869_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.c5:
+        print(json.dumps({"stiff_512cubed": stiff_512(lkp, torch, args.c5_tol, 2000, args.c5_minutes)}),
+              flush=True)
+        return
     shape = (1024, 1024)
     lattice, order, kn, precision = "D2Q81", 5, 0.1, "f64"
     s = W.poisson_source("blobs2d", shape, seed=12345)

@@ -289,7 +289,7 @@ lkp_status lkp_group_add(lkp_group *g, lkp_handle *h, const lkp_solve_opts *o) {
   h->gstate = LKP_MEMBER_RUNNING;
   h->g_sweeps = 0;
   h->trk = Tracker();
-  h->ir = IrState();
+  ir_reset(h);
   h->split = g->P;
   h->tuned = true;
   g->members.push_back(h);

@@ -254,7 +254,21 @@ lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lk
   return ir_begin_inner(h, o);
 }
 
-int ir_inner_mode(const lkp_handle *h) { return h->ir.outer == 0 ? MODE_F32 : MODE_INNER; }
+int ir_inner_mode(const lkp_handle *h) { return h->ir.first ? MODE_F32 : MODE_INNER; }
+
+void ir_reset(lkp_handle *h) {
+  const IrState old = h->ir;
+  h->ir = IrState();
+  if (h->x_nonzero) {  // resume: refine the current x, starting from its residual
+    h->ir.phase = IR_RESID;
+    h->ir.first = false;
+    // the last correction and the residual before it: the first residual of
+    // the resumed solve already gives an error estimate
+    h->ir.corr_prev = old.corr_prev;
+    h->ir.rnorm_prev = old.rnorm_prev;
+    h->ir.est = old.est;
+  }
+}
 
 SweepParams ir_inner_params(lkp_handle *h, int P) {
   SweepParams p = base_params(h);
@@ -267,6 +281,8 @@ SweepParams ir_inner_params(lkp_handle *h, int P) {
   (void)P;
   return p;
 }
+
+lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep);
 
 lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
                           const lkp_solve_opts &o, lkp_solve_report *rep) {
@@ -298,7 +314,15 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
       (!h->bf16dev() && s.rate > 0 && s.rate < 1) ? 2.0 * 5.96e-8 / (1 - s.rate) : 0.0;
   const double goal = std::max(s.inner_tol, floor32);
   if (!(s.corr == 0 || est <= goal * s.corr || s.stall >= 2)) return LKP_OK;
-  // inner solve done: x += d - phi_i mean(d), FP64 (scalar state: x += d - mean(d))
+  return ir_apply_correction(h, rep);
+}
+
+// x += d - phi_i mean(d), FP64 (scalar state: x += d - mean(d)); next: residual.
+// Also used when max_sweeps ends an inner solve early: the partial correction
+// (a truncated sum of the contraction's powers applied to r) still lowers the
+// error, and a later solve resumes from the updated x.
+lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep) {
+  IrState &s = h->ir;
   const int q = h->scalar ? 1 : h->Q;
   const size_t QN = (size_t)q * h->ncells;
   unsigned nb = 0;
@@ -317,6 +341,8 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
                                  h->ncells, h->stream, h->inplace ? h->opp_dev : nullptr));
   }
   s.outer += 1;
+  s.first = false;
+  h->x_nonzero = true;
   s.corr_prev = s.corr;
   s.rnorm_prev = s.rnorm;
   s.phase = IR_RESID;
@@ -1053,7 +1079,7 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
     if (!(o->tol_rel_l2 > 0)) return fail(LKP_ERR_ARG, "refinement (F32_IR, BF16DEV_IR) needs tol_rel_l2");
     h->dev_plain = false;
     // a resumed solve starts a fresh refinement from the current x
-    h->ir = IrState();
+    ir_reset(h);
     int K = std::max(2, o->check_every);
     if (h->inplace) K += K & 1;  // corrections end each chunk in the swapped layout
     bool converged = false;
@@ -1068,6 +1094,8 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
         if (result || converged) break;
       }
       if (h->total_sweeps - start >= o->max_sweeps) {
+        if (h->ir.phase == IR_INNER && h->ir.t_in > 0)  // keep the inner work done so far
+          if (lkp_status st = ir_apply_correction(h, &rep)) return st;
         result = fail(LKP_ERR_NOT_CONVERGED, "refinement: max_sweeps reached");
         break;
       }
@@ -1079,7 +1107,7 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
           stencil_weights(h, true, &p);
           p.xin = h->d32[h->ir.dc];
           p.xout = h->d32[1 - h->ir.dc];
-          p.src = h->ir.outer == 0 ? (const void *)h->S32 : (const void *)h->r32;
+          p.src = h->ir.first ? (const void *)h->S32 : (const void *)h->r32;
           HIP_TRY(launch_stencil(h->lattice, SMODE_F32, j == K - 1 ? FLAG_REDUCE : 0, p, h->stream));
           h->ir.dc = 1 - h->ir.dc;
         }
@@ -1097,7 +1125,7 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
           p.nout = h->dn[1 - h->ir.dc];
           p.phin = h->dphi[h->ir.dc];
           p.phout = h->dphi[1 - h->ir.dc];
-          const bool inner = h->ir.outer > 0;
+          const bool inner = !h->ir.first;
           p.src = inner ? h->r32 : h->S32;
           hipError_t e = launch_dev(h->lattice, inner, j == K - 1 ? FLAG_REDUCE : 0, p, h->stream);
           if (e != hipSuccess) return fail(LKP_ERR_HIP, "deviation sweep launch: %s", hipGetErrorString(e));
@@ -1355,6 +1383,7 @@ lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_
     HIP_TRY(hipMemcpyAsync(dstp, src, QN * 8, kind, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
   }
+  if (h->refined()) h->x_nonzero = true;  // a later solve refines this state
   h->phi_sweep[0] = h->phi_sweep[1] = -1;
   return LKP_OK;
 }

@@ -42,10 +42,12 @@ struct Tracker {
 // Iterative-refinement controller state of one F32_IR problem.
 // IR_START: the first solve (from x = 0) has the plain source chi_i S, so it
 // runs the plain FP32 sweep; later corrections solve with the population
-// residual r as source (MODE_INNER).
+// residual r as source (MODE_INNER).  A refinement resumed on a state that is
+// not zero starts at IR_RESID with first = false.
 enum IrPhase : int { IR_START = 0, IR_RESID = 1, IR_INNER = 2, IR_DONE = 3 };
 struct IrState {
   int phase = IR_START;
+  bool first = true;          // the next inner solve is the first solve from x = 0
   int outer = 0;
   double rnorm = -1.0, rnorm_prev = -1.0;
   double corr = 0.0, corr_prev = -1.0;
@@ -91,6 +93,7 @@ struct lkp_handle {
   uint16_t *dn[2] = {nullptr, nullptr};
   float *dphi[2] = {nullptr, nullptr};
   bool inplace = false;     // LKP_FLAG_IN_PLACE: f[1] == f[0] (d32[1] == d32[0] for F32_IR)
+  bool x_nonzero = false;   // refinement: x has been updated or set (not the zero state)
   int *opp_dev = nullptr;   // in place + F32_IR: opposite-velocity map for the update
   int dev_cur = 0;          // current (dn, dphi) of plain deviation sweeps (lkp_step)
   bool dev_plain = false;   // Phi comes from plain deviation sweeps (lkp_step since the last solve)
@@ -150,6 +153,7 @@ lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lk
                              lkp_solve_report *rep, bool *converged);
 lkp_status ir_begin_inner(lkp_handle *h, const lkp_solve_opts &o);  // d = 0, tolerance
 int ir_inner_mode(const lkp_handle *h);             // MODE_F32 (first solve) or MODE_INNER
+void ir_reset(lkp_handle *h);                       // fresh controller for the current x
 SweepParams ir_inner_params(lkp_handle *h, int P);  // inner sweep d[dc] -> d[1-dc]
 lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
                           const lkp_solve_opts &o, lkp_solve_report *rep);

@@ -286,3 +286,25 @@ def test_full_size_config2_refinement_precisions(precision):
     say("full size", precision, "sweeps", rep["sweeps"], "outer", rep["outer"],
         "est", rep["est_rel_err"], "true err", err)
     assert err <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["f32_ir", "bf16dev_ir"])
+def test_refinement_resumes_from_current_state(precision):
+    """A refinement stopped by max_sweeps and solved again continues from the
+    current x (its residual first): it reaches the fixed point, and the two
+    calls together take about the sweeps of one uninterrupted solve."""
+    s = _blobs((48, 40), seed=3)
+    tau = OL.tau_from_knudsen(0.1, OL.get("D2Q81"), 40)
+    ref = SP.fixed_point("D2Q81", 5, tau, s)
+    with lkp.Problem(s, "D2Q81", 5, knudsen=0.1, precision=precision) as p:
+        one = p.solve(tol_rel_l2=1e-10, check_every=20, max_sweeps=400000)
+    with lkp.Problem(s, "D2Q81", 5, knudsen=0.1, precision=precision) as p:
+        a = p.solve(tol_rel_l2=1e-10, check_every=20, max_sweeps=one["sweeps"] // 2,
+                    raise_on_error=False)
+        assert a["status"] != 0
+        b = p.solve(tol_rel_l2=1e-10, check_every=20, max_sweeps=400000)
+        phi = p.phi_host()
+    err = rel_l2(phi, ref)
+    say("resume", precision, "one solve", one["sweeps"], "split", a["sweeps"], b["sweeps"], "err", err)
+    assert err <= 1e-9
+    assert a["sweeps"] + b["sweeps"] <= 1.5 * one["sweeps"] + 200
