@@ -67,6 +67,7 @@ double now_s() {
 int default_split(int Q, int mode) {
   const bool wide = (mode == MODE_F64 || mode == MODE_RESID);
   if (Q <= 25) return 1;
+  if (mode == MODE_INNER) return inner_split(Q);
   if (wide) return Q >= 169 ? 4 : 2;
   return Q >= 169 ? 2 : 1;
 }

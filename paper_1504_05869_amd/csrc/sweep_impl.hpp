@@ -190,6 +190,17 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
     });
     // moment in velocity order, FP64
     static_for<lo, hi>([&](auto I) { part += (double)vals[(int)I - lo]; });
+    if constexpr (MT::POPSRC) {
+      // correction sweeps: fold the population source in now, (1 - omega) f_i
+      // + r_i, so that the r_i loads overlap the pulled loads instead of
+      // waiting one by one after the moment
+      const TC om1 = (TC)p.om1;
+      static_for<lo, hi>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const TSRC ri = ld<TSRC>(src + (size_t)i * plane * sizeof(TSRC), cc * (unsigned)sizeof(TSRC));
+        vals[i - lo] = (TIN)(om1 * (TC)vals[i - lo] + (TC)ri);
+      });
+    }
   };
   if constexpr (P == 1) {
     load_group(std::integral_constant<int, 0>{});
@@ -217,6 +228,19 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
   if constexpr (!MT::POPSRC) sc = (TC)ld<TSRC>(src, cc * (unsigned)sizeof(TSRC));
   double r2 = 0.0;
 
+  if constexpr (AA == 1 || (AA == 2 && MT::RESID)) {
+    // In-place stores (and the pushed reads of the residual) reuse the pull
+    // offsets of the opposite velocities; left alone the compiler keeps all Q
+    // of them live from the loads, doubling the registers.  An empty asm
+    // makes the wrapped coordinates opaque, so the offsets are recomputed.
+#pragma unroll
+    for (int j = 0; j < 2 * VMX + 1; ++j) asm volatile("" : "+v"(xw[j]));
+#pragma unroll
+    for (int j = 0; j < 2 * VMY + 1; ++j) asm volatile("" : "+v"(yw[j]));
+#pragma unroll
+    for (int j = 0; j < 2 * VMZ + 1; ++j) asm volatile("" : "+v"(zw[j]));
+  }
+
   auto store_group = [&](auto Gc) {
     constexpr int G = decltype(Gc)::value;
     constexpr int lo = G * QG;
@@ -225,8 +249,7 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
       constexpr int i = decltype(I)::value;
       TC val;
       if constexpr (MT::POPSRC) {
-        const TSRC ri = ld<TSRC>(src + (size_t)i * plane * sizeof(TSRC), cc * (unsigned)sizeof(TSRC));
-        val = om1 * (TC)vals[i - lo] + coef.wphi(i) * phic + (TC)ri;
+        val = (TC)vals[i - lo] + coef.wphi(i) * phic;  // vals holds (1 - omega) f_i + r_i
       } else {
         val = om1 * (TC)vals[i - lo] + coef.wphi(i) * phic + coef.chi(i) * sc;
       }
