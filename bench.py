@@ -43,10 +43,10 @@ def r_q(lkp, lattice: str) -> int:
 
 
 def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=None,
-               sweeps=200, chunks=1, population_sweep=False):
+               sweeps=200, chunks=1, population_sweep=False, in_place=False):
     """Average duration of one sweep (HIP events on the solver's stream)."""
     with lkp.Problem(s, lattice, order, knudsen=knudsen, tau_lb=tau_lb, precision=precision,
-                     population_sweep=population_sweep) as p:
+                     population_sweep=population_sweep, in_place=in_place) as p:
         p.step(2)
         p.sync()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -64,7 +64,8 @@ def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=No
             "gbs": n * bpc / (ms * 1e-3) / 1e9,
             "frac_hbm": n * bpc / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "velocity_groups": info["velocity_groups"], "tau_lb": info["tau_lb"],
-            "form": "stencil (tau_lb=1)" if info["scalar_stencil"] else "population sweep"}
+            "form": "stencil (tau_lb=1)" if info["scalar_stencil"] else
+                    ("population sweep, in place" if in_place else "population sweep")}
 
 
 KERNEL_SOURCES = ["paper_1504_05869_amd/csrc/sweep_impl.hpp", "paper_1504_05869_amd/csrc/lattices.hpp",
@@ -289,10 +290,17 @@ def main():
             for prec in ("f64", "f32"):
                 r = sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200)
                 extras.append(r)
+        # in place (one population buffer): every sweep pair gathers/scatters once
+        for prec in ("f64", "f32"):
+            extras.append(sweep_rate(lkp, torch, s, lattice, order, prec, knudsen=kn, sweeps=200,
+                                     in_place=True))
         s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
         for prec in ("f32", "f64"):
             extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
                                           sweeps=40, population_sweep=True), grid="256^3"))
+            extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
+                                          sweeps=40, population_sweep=True, in_place=True),
+                               grid="256^3"))
         # BF16 deviation storage (ablation): plain deviation sweeps on the
         # headline problem; bytes = n_i read + write (BF16), Phi read + write
         # and S (FP32)
