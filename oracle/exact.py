@@ -117,21 +117,32 @@ class ExactLattice:
             else:
                 self.w = [sp.expand(w1[abs(vec[0])] * w1[abs(vec[1])]) for vec in self.v]
             return
-        if name == "D3Q111":
-            shells = [b for b, _ in L.D3Q111_SHELLS]
+        if name == "D3Q111" or name in L.GENERATED_SHELLS:
+            if name == "D3Q111":
+                shells = [b for b, _ in L.D3Q111_SHELLS]
+                classes = L._D3_CLASSES
+            else:
+                from . import generator as G
+                shells = L.GENERATED_SHELLS[name]
+                classes = G.classes(len(shells[0]), L.generated_degree(name))
             orbits = [L._orbit(b) for b in shells]
-            classes = L._D3_CLASSES
+            ns = len(shells)
 
             def mom(j, e):
-                return sum(sp.Integer(x) ** e[0] * sp.Integer(y) ** e[1]
-                           * sp.Integer(z) ** e[2] for x, y, z in orbits[j])
-            idx = list(range(len(shells)))
-            # ten independent classes fix the weights, the remaining one
-            # fixes t (the first ten alone are linearly dependent)
+                r = sp.Integer(0)
+                for vec in orbits[j]:
+                    m = sp.Integer(1)
+                    for x, a in zip(vec, e):
+                        m *= sp.Integer(x) ** a
+                    r += m
+                return r
+            idx = list(range(ns))
+            # len(shells) independent classes fix the weights, the remaining
+            # one fixes t
             for drop in reversed(range(len(classes))):
                 use = [c for k, c in enumerate(classes) if k != drop]
-                A = sp.Matrix(10, 10, lambda r, j: mom(idx[j], use[r]))
-                if A.rank() == 10:
+                A = sp.Matrix(ns, ns, lambda r, j: mom(idx[j], use[r]))
+                if A.rank() == ns:
                     break
             W = _shell_weights(idx, use, mom)
             e = classes[drop]

@@ -78,6 +78,38 @@ D3Q111_SHELLS = [
 ]
 
 
+#: Velocity sets produced by the quadrature-condition search of
+#: ``oracle.generator`` (Sec. 3's systematic construction): the smallest sets
+#: whose shell weights are positive and which reproduce every Gaussian moment
+#: of degree <= 9 (N = 5) or <= 13 (N = 7).
+#:   D2Q37   N <= 5, components <= 3: the most compact of four 37-velocity sets;
+#:           stable for tau_lb >= 0.62 at N = 5.
+#:   D2Q77   N <= 7, components <= 5: the smallest set stable at N = 7.
+#:   D3Q103  the smallest 3D set for degree 9 (components <= 3); stable at N = 1
+#:           and 3 but not at N = 5 (the checkerboard mode grows at every tau).
+#:   D3Q107  the smallest 3D set that is also stable at N = 5 (tau_lb >= 0.65).
+#: The paper's D3Q111 shells satisfy the same conditions with 111 velocities.
+GENERATED_SHELLS = {
+    "D2Q37": [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1)],
+    "D2Q77": [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (4, 0),
+              (4, 1), (3, 3), (5, 0), (4, 4), (5, 3)],
+    "D3Q103": [(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 0, 0), (2, 1, 0), (2, 2, 0), (3, 0, 0),
+               (3, 1, 1), (2, 2, 2), (3, 3, 3)],
+    "D3Q107": [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 0, 0), (2, 1, 0), (2, 2, 0),
+               (3, 0, 0), (3, 1, 1), (2, 2, 2)],
+}
+
+
+def generated_degree(name: str) -> int:
+    """Moment degree whose even classes number one more than the set's shells."""
+    from . import generator as G
+    shells = GENERATED_SHELLS[name]
+    deg = 0
+    while len(G.classes(len(shells[0]), deg)) < len(shells) + 1:
+        deg += 2
+    return deg
+
+
 def _dfact(n: int) -> int:
     """(n)!! with (-1)!! = 1."""
     r = 1
@@ -246,6 +278,26 @@ def _lattice_d3q111():
     return lat
 
 
+def _lattice_generated(name):
+    """A generated set: c_s^2 and shell weights from the generator's solve."""
+    from . import generator as G
+    shells = GENERATED_SHELLS[name]
+    dim = len(shells[0])
+    deg = generated_degree(name)
+    sols = G.solve_subset(shells, G.classes(dim, deg))
+    if len(sols) != 1:
+        raise RuntimeError(f"{name}: {len(sols)} admissible solutions")
+    c2, W = sols[0]
+    v, w = [], []
+    for b, Wj in zip(shells, W):
+        for vec in _orbit(b):
+            v.append(vec)
+            w.append(Wj)
+    lat = Lattice(name, dim, np.array(v, dtype=np.int64), w, c2, 7 if deg >= 12 else 5)
+    lat.notes["shell_weights"] = list(W)
+    return lat
+
+
 _CACHE: dict = {}
 
 
@@ -264,6 +316,8 @@ def get(name: str) -> Lattice:
             lat = _standard_2d(name)
         elif name == "D3Q111":
             lat = _lattice_d3q111()
+        elif name in GENERATED_SHELLS:
+            lat = _lattice_generated(name)
         else:
             raise KeyError(name)
         _CACHE[name] = lat
