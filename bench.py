@@ -290,6 +290,11 @@ def main():
             for prec in ("f64", "f32"):
                 r = sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200)
                 extras.append(r)
+        # generated minimal sets (square-symmetric shells) for the same orders
+        for N, lat in ((5, "D2Q37"), (7, "D2Q77")):
+            for prec in ("f64", "f32"):
+                extras.append(dict(sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200),
+                                   form="generated set"))
         # in place (one population buffer): every sweep pair gathers/scatters once
         for prec in ("f64", "f32"):
             extras.append(sweep_rate(lkp, torch, s, lattice, order, prec, knudsen=kn, sweeps=200,

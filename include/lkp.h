@@ -66,7 +66,9 @@ typedef enum lkp_lattice {
   LKP_D2Q81 = 6,  /* N <= 5 */
   LKP_D2Q169 = 7, /* N <= 7 */
   LKP_D3Q111 = 8, /* N <= 5 */
-  LKP_NUM_LATTICES = 9
+  LKP_D2Q37 = 9,  /* N <= 5: generated minimal 2D set (quadrature conditions of Sec. 3) */
+  LKP_D2Q77 = 10, /* N <= 7: generated minimal 2D set stable at N = 7 */
+  LKP_NUM_LATTICES = 11
 } lkp_lattice;
 
 typedef enum lkp_precision {

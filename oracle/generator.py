@@ -28,6 +28,7 @@ from dataclasses import dataclass
 
 import mpmath as mp
 import numpy as np
+from threadpoolctl import threadpool_limits
 
 DPS = 50
 
@@ -182,10 +183,12 @@ def spectral_radius(found: Found, order: int, tau_lb: float, nk: int = 8) -> flo
     om = 1.0 / tau_lb
     worst = 0.0
     ks = np.linspace(0.0, 2.0 * np.pi, nk, endpoint=False)
-    for k in itertools.product(ks, repeat=found.dim):
-        e = np.exp(-1j * (V @ np.array(k)))
-        M = (1.0 - om) * np.diag(e) + om * np.outer(phi, e)
-        worst = max(worst, float(np.max(np.abs(np.linalg.eigvals(M)))))
+    # many small eigenproblems: BLAS threads only contend here
+    with threadpool_limits(1):
+        for k in itertools.product(ks, repeat=found.dim):
+            e = np.exp(-1j * (V @ np.array(k)))
+            M = (1.0 - om) * np.diag(e) + om * np.outer(phi, e)
+            worst = max(worst, float(np.max(np.abs(np.linalg.eigvals(M)))))
     return worst
 
 

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblkp.so")
-LATTICES = ["d1q5", "d1q9", "d1q13", "d2q5", "d2q9", "d2q25", "d2q81", "d2q169", "d3q111"]
+LATTICES = ["d1q5", "d1q9", "d1q13", "d2q5", "d2q9", "d2q25", "d2q81", "d2q169", "d3q111",
+            "d2q37", "d2q77"]
 # largest first so the parallel build finishes early
 SOURCES = (["sweep_d2q169.hip", "sweep_d3q111.hip", "sweep_d2q81.hip"]
            + [f"sweep_{l}.hip" for l in LATTICES if l not in ("d2q169", "d3q111", "d2q81")]

@@ -16,6 +16,9 @@
 //          again under the label c_s^2)
 //   D3Q111 the value at which all eleven cubic moment classes of degree <= 8
 //          hold with ten shell weights (Table vector2 does not print it)
+//   D2Q37, D2Q77  generated shell sets (Sec. 3's systematic construction):
+//          the value at which all 9 (degree <= 10) resp. 16 (degree <= 14)
+//          square-symmetric moment classes hold with 8 resp. 15 shell weights
 //   D2Q5, D2Q9  1/3 (standard nearest-neighbour sets)
 //
 // phi_i / w_i and chi_i / w_i in the radial Hermite polynomials of
@@ -28,8 +31,11 @@
 //   N=7: 1 - R4/8 + R6/24, 1 - R2/2 + R4/8 - R6/48
 #include "constants.hpp"
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
+#include <map>
 
 namespace lkp {
 namespace {
@@ -171,70 +177,107 @@ bool base_1d(int id, Base1D* b, ld* t) {
   return true;
 }
 
-bool d3q111_constants(const VelTable& T, ld* t_out, std::vector<ld>* w_out) {
-  // the eleven even cubic classes x^a y^b z^c (a >= b >= c), degree <= 8
-  static const int cls[11][3] = {{0, 0, 0}, {2, 0, 0}, {4, 0, 0}, {2, 2, 0}, {6, 0, 0}, {4, 2, 0},
-                                 {2, 2, 2}, {8, 0, 0}, {6, 2, 0}, {4, 4, 0}, {4, 2, 2}};
-  // shell index of each velocity: shells are contiguous in the table
+// Shell sets (D3Q111 and the generated 2D sets): one weight per shell of
+// signed permutations.  The weights and c_s^2 are fixed by the even moment
+// classes x1^a1 ... xd^ad (a1 >= ... >= ad, all even) of total degree <= D,
+// D the smallest degree with one class more than shells.  Dropping one class
+// leaves a square system for the weights at a given t; c_s^2 is the t at which
+// the dropped class holds as well, taken where every weight is positive.
+bool shell_constants(const VelTable& T, ld* t_out, std::vector<ld>* w_out) {
+  const int d = T.dim;
+  // shell index of each velocity (key: sorted absolute components)
   std::vector<int> shell_of(T.q);
-  int nsh = 0;
-  {
-    int prev = -1;
-    for (int i = 0; i < T.q; ++i) {
-      int a[3] = {std::abs(T.v[i][0]), std::abs(T.v[i][1]), std::abs(T.v[i][2])};
-      std::sort(a, a + 3);
-      const int key = a[0] * 100 + a[1] * 10 + a[2];
-      if (key != prev) { ++nsh; prev = key; }
-      shell_of[i] = nsh - 1;
-    }
+  std::map<long, int> shell_id;
+  for (int i = 0; i < T.q; ++i) {
+    int a[3] = {std::abs(T.v[i][0]), std::abs(T.v[i][1]), std::abs(T.v[i][2])};
+    std::sort(a, a + 3);
+    const long key = (a[2] * 64L + a[1]) * 64L + a[0];
+    auto it = shell_id.find(key);
+    if (it == shell_id.end()) it = shell_id.emplace(key, (int)shell_id.size()).first;
+    shell_of[i] = it->second;
   }
-  if (nsh != 10) return false;
-  std::vector<ld> M(11 * 10, 0.0L);  // class moment of each shell's orbit
-  for (int r = 0; r < 11; ++r)
+  const int nsh = (int)shell_id.size();
+  // even classes of the smallest degree with nsh + 1 of them
+  std::vector<std::array<int, 3>> cls;
+  for (int deg = 0; deg <= 24 && (int)cls.size() < nsh + 1; deg += 2) {
+    cls.clear();
+    for (int a0 = 0; a0 <= deg; a0 += 2)
+      for (int a1 = 0; a1 <= (d >= 2 ? a0 : 0); a1 += 2)
+        for (int a2 = 0; a2 <= (d >= 3 ? a1 : 0); a2 += 2)
+          if (a0 + a1 + a2 <= deg) cls.push_back({a0, a1, a2});
+  }
+  const int nc = (int)cls.size();
+  if (nc != nsh + 1) return false;
+  std::vector<ld> M((size_t)nc * nsh, 0.0L);  // class moment of each shell's orbit
+  for (int r = 0; r < nc; ++r)
     for (int i = 0; i < T.q; ++i) {
       ld m = 1;
-      for (int a = 0; a < 3; ++a) m *= std::pow((ld)T.v[i][a], (ld)cls[r][a]);
-      M[r * 10 + shell_of[i]] += m;
+      for (int a = 0; a < d; ++a) m *= std::pow((ld)T.v[i][a], (ld)cls[r][a]);
+      M[(size_t)r * nsh + shell_of[i]] += m;
     }
-  // pick ten independent classes: drop one class, from the last, until the
-  // remaining 10 x 10 system is solvable with a healthy pivot
+  // drop one class, from the last, until the remaining square system is
+  // solvable with a healthy pivot
   int drop = -1;
-  std::vector<ld> W;
-  for (int d = 10; d >= 0 && drop < 0; --d) {
-    std::vector<ld> A, b(10, 1.0L);
-    for (int r = 0; r < 11; ++r)
-      if (r != d)
-        for (int j = 0; j < 10; ++j) A.push_back(M[r * 10 + j]);
+  for (int dr = nc - 1; dr >= 0 && drop < 0; --dr) {
+    std::vector<ld> A, b(nsh, 1.0L);
+    for (int r = 0; r < nc; ++r)
+      if (r != dr)
+        for (int j = 0; j < nsh; ++j) A.push_back(M[(size_t)r * nsh + j]);
     std::vector<ld> x;
-    if (!solve(A, b, 10, &x)) continue;
+    if (!solve(A, b, nsh, &x)) continue;
     bool ok = true;
     for (ld v : x) ok = ok && std::isfinite(v) && std::fabs(v) < 1e12L;
-    if (ok) drop = d;
+    if (ok) drop = dr;
   }
   if (drop < 0) return false;
   auto weights_at = [&](ld tt, std::vector<ld>* x) {
     std::vector<ld> A, b;
-    for (int r = 0; r < 11; ++r)
+    for (int r = 0; r < nc; ++r)
       if (r != drop) {
-        for (int j = 0; j < 10; ++j) A.push_back(M[r * 10 + j]);
-        b.push_back(gauss(cls[r], 3, tt));
+        for (int j = 0; j < nsh; ++j) A.push_back(M[(size_t)r * nsh + j]);
+        b.push_back(gauss(cls[r].data(), d, tt));
       }
-    return solve(A, b, 10, x);
+    return solve(A, b, nsh, x);
   };
   auto resid = [&](ld tt) {
     std::vector<ld> x;
-    weights_at(tt, &x);
+    if (!weights_at(tt, &x)) return (ld)NAN;
     ld m = 0;
-    for (int j = 0; j < 10; ++j) m += M[drop * 10 + j] * x[j];
-    return m - gauss(cls[drop], 3, tt);
+    for (int j = 0; j < nsh; ++j) m += M[(size_t)drop * nsh + j] * x[j];
+    return m - gauss(cls[drop].data(), d, tt);
   };
-  ld t;
-  if (!secant(resid, 0.69L, 0.70L, &t)) return false;
-  if (!weights_at(t, &W)) return false;
-  w_out->resize(T.q);
-  for (int i = 0; i < T.q; ++i) (*w_out)[i] = W[shell_of[i]];
-  *t_out = t;
-  return true;
+  // scan t for sign changes, refine each by bisection, keep the root with
+  // positive weights
+  const ld step = 0.005L;
+  ld lo = 0.05L, flo = resid(lo);
+  for (ld hi = lo + step; hi <= 3.0L; hi += step) {
+    const ld fhi = resid(hi);
+    if (std::isfinite(flo) && std::isfinite(fhi) && (flo == 0 || flo * fhi < 0)) {
+      ld a = lo, b = hi, fa = flo;
+      for (int it = 0; it < 200 && b - a > 1e-19L * b; ++it) {
+        const ld m = 0.5L * (a + b), fm = resid(m);
+        if (fa * fm <= 0) b = m;
+        else { a = m; fa = fm; }
+      }
+      const ld t = 0.5L * (a + b);
+      std::vector<ld> W;
+      // a sign change across a pole of the reduced system is no root
+      const ld scale = std::fabs(gauss(cls[drop].data(), d, t));
+      if (std::fabs(resid(t)) < 1e-12L * scale && weights_at(t, &W)) {
+        bool pos = true;
+        for (ld w : W) pos = pos && w > 0;
+        if (pos) {
+          w_out->resize(T.q);
+          for (int i = 0; i < T.q; ++i) (*w_out)[i] = W[shell_of[i]];
+          *t_out = t;
+          return true;
+        }
+      }
+    }
+    lo = hi;
+    flo = fhi;
+  }
+  return false;
 }
 
 }  // namespace
@@ -253,7 +296,7 @@ bool lattice_constants(int id, LatticeConstants* out) {
     }
     return true;
   }
-  if (id == D3Q111) return d3q111_constants(T, &out->cs2, &out->w);
+  if (id == D3Q111 || id == D2Q37 || id == D2Q77) return shell_constants(T, &out->cs2, &out->w);
   Base1D b;
   ld t;
   if (!base_1d(id, &b, &t)) return false;

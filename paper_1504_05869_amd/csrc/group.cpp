@@ -106,6 +106,8 @@ lkp_status launch_batched(lkp_group *g, int mode, int flags, const std::vector<S
     case 81: return launch_slots<81>(g, mode, flags, slots);
     case 111: return launch_slots<111>(g, mode, flags, slots);
     case 169: return launch_slots<169>(g, mode, flags, slots);
+    case 37: return launch_slots<37>(g, mode, flags, slots);
+    case 77: return launch_slots<77>(g, mode, flags, slots);
   }
   return fail(LKP_ERR_UNSUPPORTED, "no batched sweep for Q = %d", g->Q);
 }

@@ -91,6 +91,7 @@ struct BatchParams {
 static_assert(sizeof(BatchParams<169>) <= 4096, "batched launch arguments exceed 4 KiB");
 static_assert(sizeof(BatchParams<111>) <= 4096, "batched launch arguments exceed 4 KiB");
 static_assert(sizeof(BatchParams<5>) <= 4096, "batched launch arguments exceed 4 KiB");
+static_assert(sizeof(BatchParams<77>) <= 4096, "batched launch arguments exceed 4 KiB");
 
 // ---- omega = 1: the sweep as a scalar stencil on Phi --------------------
 enum StencilMode : int {

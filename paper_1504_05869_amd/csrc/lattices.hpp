@@ -8,12 +8,18 @@
 //     D2Q5 and D2Q9 are the standard nearest-neighbour sets.
 //   3D: D3Q111 (Appendix A, Table vector2), ten shells of signed
 //     permutations, N <= 5.
+//   Generated 2D sets (Sec. 3's construction from the quadrature conditions:
+//     the smallest shell sets with positive weights reproducing every Gaussian
+//     moment to the needed degree, stable at their order):
+//     D2Q37 = shells (0,0) (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,1), N <= 5;
+//     D2Q77 = shells (0,0) (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,1) (3,2)
+//             (4,0) (4,1) (3,3) (5,0) (4,4) (5,3), N <= 7.
 #pragma once
 
 namespace lkp {
 
 enum LatticeId : int {
-  D1Q5 = 0, D1Q9, D1Q13, D2Q5, D2Q9, D2Q25, D2Q81, D2Q169, D3Q111, NUM_LATTICES
+  D1Q5 = 0, D1Q9, D1Q13, D2Q5, D2Q9, D2Q25, D2Q81, D2Q169, D3Q111, D2Q37, D2Q77, NUM_LATTICES
 };
 
 constexpr int MAXQ = 169;
@@ -104,6 +110,39 @@ constexpr VelTable d3q111() {
   return t;
 }
 
+constexpr int SHELLS37[8][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}, {3, 0}, {3, 1}};
+constexpr int SHELLS77[15][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}, {3, 0}, {3, 1},
+                                 {3, 2}, {4, 0}, {4, 1}, {3, 3}, {5, 0}, {4, 4}, {5, 3}};
+
+// 2D set from shell representatives: each shell's signed permutations, shell
+// after shell.
+constexpr VelTable shells_2d(const int (*sh)[2], int nshell, int max_order) {
+  VelTable t{};
+  int k = 0;
+  for (int s = 0; s < nshell; ++s) {
+    const int start = k;
+    for (int p = 0; p < 2; ++p)
+      for (int sg = 0; sg < 4; ++sg) {
+        int c0 = p ? sh[s][1] : sh[s][0], c1 = p ? sh[s][0] : sh[s][1];
+        if (sg & 1) c0 = -c0;
+        if (sg & 2) c1 = -c1;
+        bool seen = false;
+        for (int j = start; j < k; ++j)
+          if (t.v[j][0] == c0 && t.v[j][1] == c1) seen = true;
+        if (!seen) {
+          t.v[k][0] = c0;
+          t.v[k][1] = c1;
+          t.v[k][2] = 0;
+          ++k;
+        }
+      }
+  }
+  t.q = k;
+  t.dim = 2;
+  t.max_order = max_order;
+  return t;
+}
+
 }  // namespace detail
 
 constexpr VelTable velocity_table(int id) {
@@ -117,6 +156,8 @@ constexpr VelTable velocity_table(int id) {
     case D2Q81: return detail::square(detail::S9, 9, 5);
     case D2Q169: return detail::square(detail::S13, 13, 7);
     case D3Q111: return detail::d3q111();
+    case D2Q37: return detail::shells_2d(detail::SHELLS37, 8, 5);
+    case D2Q77: return detail::shells_2d(detail::SHELLS77, 15, 7);
     default: return VelTable{};
   }
 }
@@ -209,6 +250,8 @@ struct Lattice {
 static_assert(velocity_table(D3Q111).q == 111, "Table vector2 lists 111 velocities");
 static_assert(velocity_table(D2Q169).q == 169, "");
 static_assert(velocity_table(D2Q81).q == 81, "");
+static_assert(velocity_table(D2Q37).q == 37, "eight shells of 1, 4, 4, 4, 8, 4, 4, 8 velocities");
+static_assert(velocity_table(D2Q77).q == 77, "fifteen shells");
 static_assert(num_orbits(velocity_table(D3Q111)) == 10, "Table vector2 has ten weight classes");
 static_assert(num_orbits(velocity_table(D2Q169)) <= 32, "stencil weights travel in scalar registers");
 

@@ -96,6 +96,8 @@ hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, 
     case D2Q81: return launch_lattice_tu<D2Q81>(mode, P, aa, flags, p, s);
     case D2Q169: return launch_lattice_tu<D2Q169>(mode, P, aa, flags, p, s);
     case D3Q111: return launch_lattice_tu<D3Q111>(mode, P, aa, flags, p, s);
+    case D2Q37: return launch_lattice_tu<D2Q37>(mode, P, aa, flags, p, s);
+    case D2Q77: return launch_lattice_tu<D2Q77>(mode, P, aa, flags, p, s);
   }
   return hipErrorInvalidValue;
 }
@@ -112,6 +114,8 @@ hipError_t launch_sweep_batch(int lattice, int mode, int P, int flags, const voi
     case D2Q81: return launch_batch_tu<D2Q81>(mode, P, flags, bp, s);
     case D2Q169: return launch_batch_tu<D2Q169>(mode, P, flags, bp, s);
     case D3Q111: return launch_batch_tu<D3Q111>(mode, P, flags, bp, s);
+    case D2Q37: return launch_batch_tu<D2Q37>(mode, P, flags, bp, s);
+    case D2Q77: return launch_batch_tu<D2Q77>(mode, P, flags, bp, s);
   }
   return hipErrorInvalidValue;
 }
@@ -127,6 +131,8 @@ hipError_t launch_stencil(int lattice, int smode, int flags, const StencilParams
     case D2Q81: return launch_stencil_tu<D2Q81>(smode, flags, p, s);
     case D2Q169: return launch_stencil_tu<D2Q169>(smode, flags, p, s);
     case D3Q111: return launch_stencil_tu<D3Q111>(smode, flags, p, s);
+    case D2Q37: return launch_stencil_tu<D2Q37>(smode, flags, p, s);
+    case D2Q77: return launch_stencil_tu<D2Q77>(smode, flags, p, s);
   }
   return hipErrorInvalidValue;
 }
