@@ -17,7 +17,7 @@
 //   D3Q111 the value at which all eleven cubic moment classes of degree <= 8
 //          hold with ten shell weights (Table vector2 does not print it)
 //   D2Q37, D2Q77  generated shell sets (Sec. 3's systematic construction):
-//          the value at which all 9 (degree <= 10) resp. 16 (degree <= 14)
+//          the value at which all 9 (degree <= 8) resp. 16 (degree <= 12)
 //          square-symmetric moment classes hold with 8 resp. 15 shell weights
 //   D2Q5, D2Q9  1/3 (standard nearest-neighbour sets)
 //
