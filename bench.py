@@ -186,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="headline and the serving stream only (no other extras)")
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=50.0)
@@ -284,7 +286,7 @@ def main():
         "last_check": {"est_rel_err": last["est_rel_err"], "rate": last["rate"]},
     }
 
-    if not args.no_extras:
+    if not args.no_extras and not args.serving_only:
         extras = []
         for N, lat in ORDERS.items():
             for prec in ("f64", "f32"):
@@ -324,7 +326,7 @@ def main():
             extras.append(r)
         out["sweeps"] = [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in e.items()}
                          for e in extras]
-    if not args.no_extras and not args.no_tts:
+    if not args.no_extras and not args.serving_only and not args.no_tts:
         # 256^3 D3Q111 N=5 at tau_lb = 1 (512 Gaussians + sine background):
         # time to rel-L2 1e-6 in FP32 + refinement and in FP64, stencil form
         s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
@@ -340,7 +342,7 @@ def main():
                              "outer": rep["outer"], "est_rel_err": rep["est_rel_err"]})
         out["time_to_solution_256cubed"] = tts3
         del s3
-    if not args.no_extras and not args.no_tts:
+    if not args.no_extras and not args.serving_only and not args.no_tts:
         # time-to-solution on the headline problem, FP64 and FP32 + refinement
         tts = []
         for prec, tol in (("f64", 1e-10), ("f32_ir", 1e-10), ("bf16dev_ir", 1e-10),
@@ -356,7 +358,7 @@ def main():
                             "est_rel_err": rep["est_rel_err"]})
         out["time_to_solution"] = tts
 
-    if not args.no_extras and not args.no_serving:
+    if (not args.no_extras or args.serving_only) and not args.no_serving:
         out["serving"] = serving_run(args.serve_requests, args.serve_rate)
 
     if not args.no_cpu:

@@ -278,9 +278,20 @@ lkp_status lkp_group_remove(lkp_group *g, lkp_handle *h);
  * the end, then report every member (running, converged or failed) into
  * out[0 .. *count) (out may be NULL when capacity is 0).  Enqueues on the
  * group's stream and synchronises it once for the read-back of all members'
- * norms (48 bytes each). */
+ * norms (48 bytes each).
+ * The batched sweeps and norm reductions of a step are replayed from a
+ * captured hipGraph when the step launches exactly (byte for byte, launch
+ * parameters included) what an earlier captured step launched: a step that
+ * repeats the previous step's launches is captured, up to 8 graphs per group
+ * are kept (least recently used evicted).  Results are bitwise those of the
+ * eager launches.  The environment variable LKP_GROUP_GRAPH=0, read at
+ * lkp_group_create, disables capture for the group. */
 lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, int32_t capacity,
                           int32_t *count);
+
+/* Counters of the group's captured steps: graphs captured and steps replayed
+ * from a graph since creation (either pointer may be NULL). */
+lkp_status lkp_group_graph_stats(const lkp_group *g, int64_t *captures, int64_t *replays);
 
 /* Destroy the group; members are released from it, not destroyed. */
 lkp_status lkp_group_destroy(lkp_group *g);

@@ -240,6 +240,13 @@ class Group:
                         "max_change": r.max_change, "phi_l2": r.phi_l2})
         return out
 
+    def graph_stats(self) -> dict:
+        """Graphs captured and steps replayed from a graph so far."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        check(self._lib.lkp_group_graph_stats(self._g, ctypes.byref(c), ctypes.byref(r)),
+              "lkp_group_graph_stats")
+        return {"captures": c.value, "replays": r.value}
+
     def close(self):
         if getattr(self, "_g", None) and self._g.value:
             self._lib.lkp_group_destroy(self._g)

@@ -21,7 +21,7 @@ EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_solve", "lkp
            "lkp_residual", "lkp_get_phi", "lkp_get_populations", "lkp_set_populations",
            "lkp_lattice_info", "lkp_get_info", "lkp_sync", "lkp_last_error",
            "lkp_group_create", "lkp_group_add", "lkp_group_remove", "lkp_group_step",
-           "lkp_group_destroy"]
+           "lkp_group_destroy", "lkp_group_graph_stats"]
 MEMBER_STATES = {0: "running", 1: "converged", 2: "failed"}
 FLAG_POPULATION_SWEEP = 1
 FLAG_IN_PLACE = 2
@@ -114,6 +114,7 @@ def load() -> ctypes.CDLL:
         "lkp_group_step": (ctypes.c_int, [H, ctypes.c_int32, P(MemberReport), ctypes.c_int32,
                                           P(ctypes.c_int32)]),
         "lkp_group_destroy": (ctypes.c_int, [H]),
+        "lkp_group_graph_stats": (ctypes.c_int, [H, P(ctypes.c_int64), P(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

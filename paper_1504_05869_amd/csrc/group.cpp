@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -23,6 +24,23 @@ struct lkp_group {
   double *norms_dev = nullptr;   // NUM_NORMS per member slot
   double *norms_host = nullptr;  // pinned mirror
   size_t cap = 0;
+
+  // Captured ticks.  A tick's launches (every batched sweep and norm finish,
+  // parameters included) are first recorded as a byte signature; a tick whose
+  // signature equals the previous tick's is captured once into a graph, and a
+  // cached graph is replayed only for an identical signature, so a replay
+  // launches exactly what the eager path would.
+  struct Graph {
+    std::vector<unsigned char> sig;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+  };
+  bool use_graph = true;
+  hipStream_t capture = nullptr;  // private stream used only to record graphs
+  std::vector<Graph> graphs;
+  std::vector<unsigned char> last_sig;
+  uint64_t clock = 0;
+  int64_t graph_replays = 0, graph_captures = 0;
 
   int mode() const {
     return precision == LKP_F64 ? MODE_F64 : (precision == LKP_F32 ? MODE_F32 : MODE_INNER);
@@ -54,8 +72,21 @@ struct Slot {
   double *phi_out;
 };
 
+// Where a tick's launches go: onto `stream`, or (sig != nullptr) appended to
+// a signature without launching anything.
+struct Sink {
+  hipStream_t stream;
+  std::vector<unsigned char> *sig;
+
+  void record(const void *p, size_t n) const {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    sig->insert(sig->end(), b, b + n);
+  }
+};
+
 template <int Q>
-lkp_status launch_slots(lkp_group *g, int mode, int flags, const std::vector<Slot> &slots) {
+lkp_status launch_slots(lkp_group *g, int mode, int flags, const std::vector<Slot> &slots,
+                        const Sink &out) {
   constexpr int cap = batch_capacity(Q);
   BatchParams<Q> bp;
   std::memset(&bp, 0, sizeof bp);
@@ -90,26 +121,104 @@ lkp_status launch_slots(lkp_group *g, int mode, int flags, const std::vector<Slo
       m.block_begin = bp.nblocks;
       bp.nblocks += m.nblocks;
     }
-    hipError_t err = launch_sweep_batch(g->lattice, mode, g->P, flags, &bp, g->stream);
+    if (out.sig) {
+      const int head[2] = {mode, flags};
+      out.record(head, sizeof head);
+      out.record(&bp, sizeof bp);
+      continue;
+    }
+    hipError_t err = launch_sweep_batch(g->lattice, mode, g->P, flags, &bp, out.stream);
     if (err != hipSuccess) return fail(LKP_ERR_HIP, "batched sweep launch: %s", hipGetErrorString(err));
   }
   return LKP_OK;
 }
 
-lkp_status launch_batched(lkp_group *g, int mode, int flags, const std::vector<Slot> &slots) {
+lkp_status launch_batched(lkp_group *g, int mode, int flags, const std::vector<Slot> &slots,
+                          const Sink &out) {
   if (slots.empty()) return LKP_OK;
   switch (g->Q) {
-    case 5: return launch_slots<5>(g, mode, flags, slots);
-    case 9: return launch_slots<9>(g, mode, flags, slots);
-    case 13: return launch_slots<13>(g, mode, flags, slots);
-    case 25: return launch_slots<25>(g, mode, flags, slots);
-    case 81: return launch_slots<81>(g, mode, flags, slots);
-    case 111: return launch_slots<111>(g, mode, flags, slots);
-    case 169: return launch_slots<169>(g, mode, flags, slots);
-    case 37: return launch_slots<37>(g, mode, flags, slots);
-    case 77: return launch_slots<77>(g, mode, flags, slots);
+    case 5: return launch_slots<5>(g, mode, flags, slots, out);
+    case 9: return launch_slots<9>(g, mode, flags, slots, out);
+    case 13: return launch_slots<13>(g, mode, flags, slots, out);
+    case 25: return launch_slots<25>(g, mode, flags, slots, out);
+    case 81: return launch_slots<81>(g, mode, flags, slots, out);
+    case 111: return launch_slots<111>(g, mode, flags, slots, out);
+    case 169: return launch_slots<169>(g, mode, flags, slots, out);
+    case 37: return launch_slots<37>(g, mode, flags, slots, out);
+    case 77: return launch_slots<77>(g, mode, flags, slots, out);
   }
   return fail(LKP_ERR_UNSUPPORTED, "no batched sweep for Q = %d", g->Q);
+}
+
+lkp_status finish_slot(lkp_group *g, lkp_handle *h, size_t k, const Sink &out) {
+  const unsigned nb = sweep_blocks(h, g->P);
+  double *dst = g->norms_dev + k * NUM_NORMS;
+  if (out.sig) {
+    const void *args[2] = {h->partials, dst};
+    out.record(args, sizeof args);
+    out.record(&nb, sizeof nb);
+    return LKP_OK;
+  }
+  return finish_norms(h, nb, dst, out.stream);
+}
+
+void drop_graph(lkp_group::Graph &e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  e.exec = nullptr;
+}
+
+// Enqueue one tick's launches (enqueue(Sink) must launch the same work on
+// every call), replaying or capturing a graph where the signature allows.
+// Every tick ends in a host synchronisation of the group's stream, so no
+// graph is in flight when one is evicted.
+template <class F>
+lkp_status run_tick(lkp_group *g, F &&enqueue) {
+  if (!g->use_graph) return enqueue(Sink{g->stream, nullptr});
+  std::vector<unsigned char> sig;
+  if (lkp_status st = enqueue(Sink{nullptr, &sig})) return st;
+  for (auto &e : g->graphs) {
+    if (e.sig == sig) {
+      e.last_use = ++g->clock;
+      LKP_HIP_TRY(hipGraphLaunch(e.exec, g->stream));
+      ++g->graph_replays;
+      return LKP_OK;
+    }
+  }
+  if (sig != g->last_sig) {  // seen once: run eagerly, capture on a repeat
+    g->last_sig = std::move(sig);
+    return enqueue(Sink{g->stream, nullptr});
+  }
+  if (!g->capture) LKP_HIP_TRY(hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking));
+  LKP_HIP_TRY(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
+  lkp_status st = enqueue(Sink{g->capture, nullptr});
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(g->capture, &graph);
+  if (st) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(LKP_ERR_HIP, "group graph capture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(LKP_ERR_HIP, "group graph instantiate: %s", hipGetErrorString(e));
+  constexpr size_t kMaxGraphs = 8;
+  if (g->graphs.size() >= kMaxGraphs) {
+    auto lru = std::min_element(g->graphs.begin(), g->graphs.end(),
+                                [](const lkp_group::Graph &a, const lkp_group::Graph &b) {
+                                  return a.last_use < b.last_use;
+                                });
+    drop_graph(*lru);
+    g->graphs.erase(lru);
+  }
+  lkp_group::Graph entry;
+  entry.sig = std::move(sig);
+  entry.exec = exec;
+  entry.last_use = ++g->clock;
+  g->graphs.push_back(std::move(entry));
+  ++g->graph_captures;
+  LKP_HIP_TRY(hipGraphLaunch(exec, g->stream));
+  return LKP_OK;
 }
 
 lkp_status read_slots(lkp_group *g, size_t n) {
@@ -127,30 +236,32 @@ void set_failed(lkp_handle *h, lkp_status st) {
 
 // K plain sweeps (F64 / F32) of every member, norms on the last two.
 lkp_status step_plain(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
-  std::vector<int> cur(run.size());
-  for (size_t k = 0; k < run.size(); ++k) cur[k] = run[k]->cur;
-  std::vector<Slot> slots(run.size());
-  for (int j = 0; j < K; ++j) {
-    int flags = 0;
-    if (j == K - 2) flags = FLAG_PHI;
-    if (j == K - 1) flags = FLAG_REDUCE;
-    for (size_t k = 0; k < run.size(); ++k) {
-      lkp_handle *h = run[k];
-      Slot &s = slots[k];
-      s.h = h;
-      s.fin = h->f[cur[k]];
-      s.fout = h->f[1 - cur[k]];
-      s.src = h->S;
-      s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
-      s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
-      cur[k] = 1 - cur[k];
+  auto enqueue = [&](const Sink &out) -> lkp_status {
+    std::vector<int> cur(run.size());
+    for (size_t k = 0; k < run.size(); ++k) cur[k] = run[k]->cur;
+    std::vector<Slot> slots(run.size());
+    for (int j = 0; j < K; ++j) {
+      int flags = 0;
+      if (j == K - 2) flags = FLAG_PHI;
+      if (j == K - 1) flags = FLAG_REDUCE;
+      for (size_t k = 0; k < run.size(); ++k) {
+        lkp_handle *h = run[k];
+        Slot &s = slots[k];
+        s.h = h;
+        s.fin = h->f[cur[k]];
+        s.fout = h->f[1 - cur[k]];
+        s.src = h->S;
+        s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
+        s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
+        cur[k] = 1 - cur[k];
+      }
+      if (lkp_status st = launch_batched(g, g->mode(), flags, slots, out)) return st;
     }
-    if (lkp_status st = launch_batched(g, g->mode(), flags, slots)) return st;
-  }
-  for (size_t k = 0; k < run.size(); ++k)
-    if (lkp_status st = finish_norms(run[k], sweep_blocks(run[k], g->P),
-                                     g->norms_dev + k * NUM_NORMS, g->stream))
-      return st;
+    for (size_t k = 0; k < run.size(); ++k)
+      if (lkp_status st = finish_slot(g, run[k], k, out)) return st;
+    return LKP_OK;
+  };
+  if (lkp_status st = run_tick(g, enqueue)) return st;
   if (lkp_status st = read_slots(g, run.size())) return st;
   for (size_t k = 0; k < run.size(); ++k) {
     lkp_handle *h = run[k];
@@ -201,33 +312,41 @@ lkp_status step_ir(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
   }
   // first solves run the plain FP32 sweep, corrections the residual-source
   // sweep: one batched launch per kind
-  std::vector<Slot> first, corr;
-  for (int j = 0; j < K; ++j) {
-    int flags = 0;
-    if (j == K - 2) flags = FLAG_PHI;
-    if (j == K - 1) flags = FLAG_REDUCE;
-    first.clear();
-    corr.clear();
-    for (size_t k = 0; k < inner.size(); ++k) {
-      lkp_handle *h = inner[k];
-      Slot s;
-      s.h = h;
-      s.fin = h->d32[h->ir.dc];
-      s.fout = h->d32[1 - h->ir.dc];
-      const bool plain = ir_inner_mode(h) == MODE_F32;
-      s.src = plain ? (const void *)h->S32 : (const void *)h->r32;
-      s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
-      s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
-      h->ir.dc = 1 - h->ir.dc;
-      (plain ? first : corr).push_back(s);
+  auto enqueue = [&](const Sink &out) -> lkp_status {
+    std::vector<int> dc(inner.size());
+    for (size_t k = 0; k < inner.size(); ++k) dc[k] = inner[k]->ir.dc;
+    std::vector<Slot> first, corr;
+    for (int j = 0; j < K; ++j) {
+      int flags = 0;
+      if (j == K - 2) flags = FLAG_PHI;
+      if (j == K - 1) flags = FLAG_REDUCE;
+      first.clear();
+      corr.clear();
+      for (size_t k = 0; k < inner.size(); ++k) {
+        lkp_handle *h = inner[k];
+        Slot s;
+        s.h = h;
+        s.fin = h->d32[dc[k]];
+        s.fout = h->d32[1 - dc[k]];
+        const bool plain = ir_inner_mode(h) == MODE_F32;
+        s.src = plain ? (const void *)h->S32 : (const void *)h->r32;
+        s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
+        s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
+        dc[k] = 1 - dc[k];
+        (plain ? first : corr).push_back(s);
+      }
+      if (lkp_status st = launch_batched(g, MODE_F32, flags, first, out)) return st;
+      if (lkp_status st = launch_batched(g, MODE_INNER, flags, corr, out)) return st;
     }
-    if (lkp_status st = launch_batched(g, MODE_F32, flags, first)) return st;
-    if (lkp_status st = launch_batched(g, MODE_INNER, flags, corr)) return st;
+    for (size_t k = 0; k < inner.size(); ++k)
+      if (lkp_status st = finish_slot(g, inner[k], k, out)) return st;
+    return LKP_OK;
+  };
+  if (!inner.empty()) {
+    if (lkp_status st = run_tick(g, enqueue)) return st;
+    if (K % 2)
+      for (lkp_handle *h : inner) h->ir.dc = 1 - h->ir.dc;
   }
-  for (size_t k = 0; k < inner.size(); ++k)
-    if (lkp_status st = finish_norms(inner[k], sweep_blocks(inner[k], g->P),
-                                     g->norms_dev + k * NUM_NORMS, g->stream))
-      return st;
   if (lkp_status st = read_slots(g, inner.size())) return st;
   for (size_t k = 0; k < inner.size(); ++k) {
     lkp_handle *h = inner[k];
@@ -265,6 +384,7 @@ lkp_status lkp_group_create(int32_t lattice, int32_t order, int32_t precision, v
     const int P = std::atoi(env);
     if (sweep_variant_available(lattice, g->mode(), P)) g->P = P;
   }
+  if (const char *env = std::getenv("LKP_GROUP_GRAPH")) g->use_graph = std::atoi(env) != 0;
   *out = g;
   return LKP_OK;
 }
@@ -340,11 +460,20 @@ lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, 
   return LKP_OK;
 }
 
+lkp_status lkp_group_graph_stats(const lkp_group *g, int64_t *captures, int64_t *replays) {
+  if (!g) return fail(LKP_ERR_ARG, "lkp_group_graph_stats: null group");
+  if (captures) *captures = g->graph_captures;
+  if (replays) *replays = g->graph_replays;
+  return LKP_OK;
+}
+
 lkp_status lkp_group_destroy(lkp_group *g) {
   if (!g) return LKP_OK;
   for (lkp_handle *h : g->members) h->group = nullptr;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
+  for (auto &e : g->graphs) drop_graph(e);
+  if (g->capture) (void)hipStreamDestroy(g->capture);
   if (g->norms_dev) (void)hipFree(g->norms_dev);
   if (g->norms_host) (void)hipHostFree(g->norms_host);
   delete g;

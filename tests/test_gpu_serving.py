@@ -101,6 +101,74 @@ def test_alone_equals_mix_bitwise(lattice, order, precision, split, specs):
         assert err <= (1e-8 if precision == "f64" else 2e-7)
 
 
+def _group(lattice, order, precision, graphs):
+    old = os.environ.get("LKP_GROUP_GRAPH")
+    os.environ["LKP_GROUP_GRAPH"] = "1" if graphs else "0"
+    try:
+        return lkp.Group(lattice, order, precision)
+    finally:
+        if old is None:
+            os.environ.pop("LKP_GROUP_GRAPH")
+        else:
+            os.environ["LKP_GROUP_GRAPH"] = old
+
+
+@pytest.mark.parametrize("lattice,order,precision", [("D2Q81", 5, "f64"), ("D2Q81", 5, "f32_ir"),
+                                                     ("D3Q111", 5, "f32"), ("D2Q37", 5, "f64")])
+def test_captured_steps_equal_eager_every_tick(lattice, order, precision):
+    """A group replaying captured steps and a group launching eagerly, fed the
+    same problems in lockstep (one joins late, members retire as they
+    converge), report bitwise the same norms after every step and end with
+    the same answers; the captured group really replays graphs."""
+    shape2 = [(40, 36), (24, 50), (32, 32)]
+    shapes = shape2 if OL.get(lattice).dim == 2 else [(10, 12, 8), (8, 8, 16), (12, 12, 12)]
+    specs = [(sh, kn, 20 + k) for k, (sh, kn) in enumerate(zip(shapes, (0.1, 0.3, 0.2)))]
+    K, tol = 10, {"f64": 1e-9, "f32_ir": 1e-7, "f32": 1e-5}[precision]
+    groups = [_group(lattice, order, precision, True), _group(lattice, order, precision, False)]
+    probs = [{}, {}]
+    done = [{}, {}]
+    try:
+        for tick in range(5000):
+            for k, (shape, kn, seed) in enumerate(specs):
+                if tick == (0 if k < 2 else 4):
+                    for j, g in enumerate(groups):
+                        p = lkp.Problem(_source(shape, seed), lattice, order, knudsen=kn,
+                                        precision=precision)
+                        g.add(p, tol_rel_l2=tol, max_sweeps=200000)
+                        probs[j][p._h.value] = (k, p)
+            if not len(groups[0]) and tick > 4:
+                break
+            reps = [g.step(K) for g in groups]
+            assert len(reps[0]) == len(reps[1])
+            for ra, rb in zip(*reps):
+                ka, kb = probs[0][ra["problem"]._h.value][0], probs[1][rb["problem"]._h.value][0]
+                assert ka == kb
+                for key in ("state", "status", "sweeps", "outer"):
+                    assert ra[key] == rb[key], (tick, key, ra, rb)
+                for key in ("est_rel_err", "max_change", "phi_l2"):
+                    assert ra[key] == rb[key] or (np.isnan(ra[key]) and np.isnan(rb[key])), \
+                        (tick, key, ra[key], rb[key])
+            for j, g in enumerate(groups):
+                for r in reps[j]:
+                    if r["state"] == "running":
+                        continue
+                    assert r["state"] == "converged", r
+                    k, p = probs[j][r["problem"]._h.value]
+                    done[j][k] = p.phi_host()
+                    g.remove(p)
+                    p.close()
+        stats = [g.graph_stats() for g in groups]
+    finally:
+        for g in groups:
+            g.close()
+    say(lattice, precision, "graph stats", stats, "ticks", tick)
+    assert sorted(done[0]) == sorted(done[1]) == list(range(len(specs)))
+    for k in done[0]:
+        assert np.array_equal(done[0][k], done[1][k])
+    assert stats[0]["captures"] >= 1 and stats[0]["replays"] >= 3
+    assert stats[1] == {"captures": 0, "replays": 0}
+
+
 def test_group_rejects_stencil_form_handles():
     """tau_lb = 1 handles keep Phi only and are driven by lkp_solve."""
     g = lkp.Group("D2Q25", 3, "f64")
