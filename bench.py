@@ -171,7 +171,9 @@ def serving_run(n_requests: int, rate: float) -> dict:
     return {"stream": f"{n_requests} requests, Poisson arrivals at {rate}/s, 2D D2Q81 N=5 "
                       "{64,128,256,512}^2 and 3D D3Q111 N=5 {32,48,64}^3, Kn~U(0.05,0.5), "
                       "Gaussian blobs, retire at estimated rel-L2 1e-6",
-            "batched_f32_ir": {k: summ[k] for k in keys} | {"ticks": summ["ticks"]},
+            "batched_f32_ir": {k: summ[k] for k in keys}
+                              | {k: summ[k] for k in ("ticks", "graph_captures", "graph_replays")
+                                 if k in summ},
             "one_at_a_time_f64": {k: bsum[k] for k in keys},
             "speedup_problems_per_s": summ["problems_per_s"] / bsum["problems_per_s"]}
 

@@ -281,9 +281,9 @@ lkp_status lkp_group_remove(lkp_group *g, lkp_handle *h);
  * norms (48 bytes each).
  * The batched sweeps and norm reductions of a step are replayed from a
  * captured hipGraph when the step launches exactly (byte for byte, launch
- * parameters included) what an earlier captured step launched: a step that
- * repeats the previous step's launches is captured, up to 8 graphs per group
- * are kept (least recently used evicted).  Results are bitwise those of the
+ * parameters included) what an earlier captured step launched: a step whose
+ * launches repeat those of the two steps before it is captured, up to 8
+ * graphs per group are kept (least recently used evicted).  Results are bitwise those of the
  * eager launches.  The environment variable LKP_GROUP_GRAPH=0, read at
  * lkp_group_create, disables capture for the group. */
 lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, int32_t capacity,

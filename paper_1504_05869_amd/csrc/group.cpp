@@ -39,6 +39,7 @@ struct lkp_group {
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<Graph> graphs;
   std::vector<unsigned char> last_sig;
+  int repeats = 0;  // consecutive steps whose signature equals last_sig
   uint64_t clock = 0;
   int64_t graph_replays = 0, graph_captures = 0;
 
@@ -184,10 +185,18 @@ lkp_status run_tick(lkp_group *g, F &&enqueue) {
       return LKP_OK;
     }
   }
-  if (sig != g->last_sig) {  // seen once: run eagerly, capture on a repeat
+  // Capture only a composition that has stayed the same for three steps: a
+  // step's launches are queued far ahead of the GPU, so a graph saves little
+  // per step and its instantiation is wasted on membership that keeps changing.
+  constexpr int kRepeatsBeforeCapture = 2;
+  if (sig == g->last_sig) {
+    ++g->repeats;
+  } else {
     g->last_sig = std::move(sig);
-    return enqueue(Sink{g->stream, nullptr});
+    g->repeats = 0;
   }
+  if (g->repeats < kRepeatsBeforeCapture) return enqueue(Sink{g->stream, nullptr});
+  sig = g->last_sig;
   if (!g->capture) LKP_HIP_TRY(hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking));
   LKP_HIP_TRY(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
   lkp_status st = enqueue(Sink{g->capture, nullptr});

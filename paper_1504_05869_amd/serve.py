@@ -99,6 +99,14 @@ class GpuBackend:
         g.add(p, tol_rel_l2=tol, max_sweeps=max_sweeps)
         return p
 
+    def graph_stats(self) -> dict:
+        """Captured graphs and graph-replayed steps over every group."""
+        tot = {"captures": 0, "replays": 0}
+        for g in self.groups.values():
+            for k, v in g.graph_stats().items():
+                tot[k] += v
+        return tot
+
     def tick(self, sweeps: int):
         """One batched step of every non-empty group; (problem, report) pairs."""
         out = []
@@ -183,8 +191,11 @@ class Server:
                 res.finished = self.clock() - t0
                 used -= fp
         out = [results[r.rid] for r in reqs]
-        return out, summarize(out, extra={"ticks": self.ticks, "peak_hbm_bytes": self.peak_used,
-                                          "hbm_budget": self.budget})
+        extra = {"ticks": self.ticks, "peak_hbm_bytes": self.peak_used, "hbm_budget": self.budget}
+        stats = getattr(self.backend, "graph_stats", None)
+        if stats is not None:
+            extra.update({"graph_" + k: v for k, v in stats().items()})
+        return out, summarize(out, extra=extra)
 
 
 def run_one_at_a_time(requests: list[Request], precision: str = "f64", tol: float = 1e-6,
