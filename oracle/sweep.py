@@ -56,12 +56,16 @@ def grid3(shape):
 class Problem:
     """One periodic Poisson problem for the oracle."""
 
-    def __init__(self, lattice: str, order: int, tau_lb: float, s: np.ndarray):
+    def __init__(self, lattice: str, order: int, tau_lb: float, s: np.ndarray, drift=None):
         self.lat = L.get(lattice)
         self.order = order
         self.tau_lb = float(tau_lb)
         self.omega = 1.0 / self.tau_lb
-        self.phi, self.chi = L.coefficients(self.lat, order)
+        if drift is None or not any(drift):
+            self.phi, self.chi = L.coefficients(self.lat, order)
+        else:  # advection-diffusion variant (oracle.drift)
+            from . import drift as DR
+            self.phi, self.chi = DR.coefficients(self.lat, order, drift)
         self.s = np.ascontiguousarray(s, dtype=np.float64)
         if self.s.ndim != self.lat.dim:
             raise ValueError("source rank must equal the lattice dimension")
