@@ -116,6 +116,20 @@ typedef struct lkp_problem_desc {
   int32_t allow_unstable;   /* 1: skip the tau_lb stability check */
   int32_t flags;            /* LKP_FLAG_* bits */
   void *stream;             /* hipStream_t for all of this handle's work; NULL = default */
+  double drift[3];          /* uniform drift u (lattice units per sweep) of the
+                               advection-diffusion variant, the extension named at the
+                               end of the paper (Sec. 5); all zero = the paper's diffusion
+                               scheme.  The equilibrium becomes that of a Gaussian moved by
+                               u, to second order in u:
+                                 phi_i += w_i [ (v_i.u)/c_s^2 + ((v_i.u)^2 - c_s^2 |u|^2)/(2 c_s^4) ]
+                               (mass, first moment u and second moment c_s^2 delta + u u), so
+                               a sweep is a time step of d_t Phi + u.grad Phi = D lap Phi + D s,
+                               D = c_s^2 (tau_lb - 1/2), and the fixed point solves
+                               lap Phi - (u/D).grad Phi = -s.  Components beyond dim must be 0
+                               and |u|^2 < c_s^2 (else LKP_ERR_ARG / LKP_ERR_UNSTABLE unless
+                               allow_unstable).  A drifted handle always sweeps populations
+                               (also at tau_lb = 1) and cannot join a group.  Zero-initialise
+                               the whole description so that older callers get u = 0. */
 } lkp_problem_desc;
 
 typedef struct lkp_handle lkp_handle;
@@ -216,6 +230,14 @@ typedef struct lkp_handle_info {
 } lkp_handle_info;
 
 lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info);
+
+/* The handle's equilibrium and source shapes phi_i, chi_i (Sec. 3, Eqs.
+ * omega:eq, chi:eq, omega:eq3, chi:eq3, with the drift terms of a drifted
+ * handle) in the order of lkp_lattice_info's velocities: Q FP64 values each
+ * into host arrays (either may be NULL).  A time-dependent run starts from an
+ * equilibrium state by lkp_set_populations with f*_i = phi_i Phi_0 and then
+ * advances with lkp_step.  Errors: LKP_ERR_ARG. */
+lkp_status lkp_get_coefficients(lkp_handle *h, double *phi, double *chi);
 
 /* Wait for all of the handle's queued work. */
 lkp_status lkp_sync(lkp_handle *h);

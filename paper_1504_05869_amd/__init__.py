@@ -99,7 +99,9 @@ class Problem:
     def __init__(self, source, lattice: str, order: int, tau_lb=None, knudsen=None,
                  precision: str = "f64", subtract_mean: bool = False,
                  allow_unstable: bool = False, stream=None, population_sweep: bool = False,
-                 in_place: bool = False):
+                 in_place: bool = False, drift=None):
+        """drift: uniform drift (ux, uy, uz) in velocity-component order (x is the
+        last array axis) for the advection-diffusion variant; None = diffusion."""
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         if isinstance(source, torch.Tensor):
@@ -121,6 +123,12 @@ class Problem:
                    | (_lib.FLAG_IN_PLACE if in_place else 0))
         self._stream = _stream_handle(stream)
         d.stream = self._stream
+        if drift is not None:
+            u = [float(x) for x in drift]
+            if len(u) > 3:
+                raise ValueError("drift has at most 3 components")
+            for a, x in enumerate(u):
+                d.drift[a] = x
         self.lattice, self.order, self.precision = lattice, int(order), precision
         check(self._lib.lkp_create(ctypes.byref(d), ctypes.byref(self._h)), "lkp_create")
         del src
@@ -191,6 +199,20 @@ class Problem:
     def set_populations(self, f) -> None:
         f = np.ascontiguousarray(f, dtype=np.float64)
         check(self._lib.lkp_set_populations(self._h, f.ctypes.data, 0), "lkp_set_populations")
+
+    def coefficients(self):
+        """(phi_i, chi_i) of this handle, in lattice_info's velocity order."""
+        q = self.info()["Q"]
+        phi, chi = np.empty(q), np.empty(q)
+        check(self._lib.lkp_get_coefficients(self._h, phi.ctypes.data, chi.ctypes.data),
+              "lkp_get_coefficients")
+        return phi, chi
+
+    def set_equilibrium(self, phi0) -> None:
+        """Start a time-dependent run from the equilibrium f*_i = phi_i Phi_0."""
+        phi, _ = self.coefficients()
+        phi0 = np.asarray(phi0, dtype=np.float64)
+        self.set_populations(phi.reshape((-1,) + (1,) * phi0.ndim) * phi0[None])
 
     def info(self) -> dict:
         i = _lib.HandleInfo()

@@ -408,6 +408,8 @@ lkp_status lkp_group_add(lkp_group *g, lkp_handle *h, const lkp_solve_opts *o) {
     return fail(LKP_ERR_UNSUPPORTED, "tau_lb = 1 stencil-form handles are solved with lkp_solve");
   if (h->inplace)
     return fail(LKP_ERR_UNSUPPORTED, "in-place (single-buffer) handles are solved with lkp_solve");
+  if (h->drift)
+    return fail(LKP_ERR_UNSUPPORTED, "drifted (advection-diffusion) handles are solved with lkp_solve");
   if (!(o->tol_rel_l2 > 0) && !(o->tol_maxchange > 0))
     return fail(LKP_ERR_ARG, "give tol_rel_l2 or tol_maxchange");
   if (h->precision == LKP_F32_IR && !(o->tol_rel_l2 > 0))

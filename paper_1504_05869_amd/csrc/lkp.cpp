@@ -482,8 +482,21 @@ lkp_status validate(const lkp_problem_desc *d, LatticeConstants *lc, double *tau
   if (!d->allow_unstable && tau < thr)
     return fail(LKP_ERR_UNSTABLE, "tau_lb = %g is below the stability limit %g for order %d", tau,
                 thr, d->order);
+  double u2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(d->drift[a])) return fail(LKP_ERR_ARG, "drift[%d] is not finite", a);
+    if (a >= d->dim && d->drift[a] != 0.0)
+      return fail(LKP_ERR_ARG, "drift[%d] must be 0 for dim %d", a, d->dim);
+    u2 += d->drift[a] * d->drift[a];
+  }
+  if (!d->allow_unstable && !(u2 < (double)lc->cs2))
+    return fail(LKP_ERR_UNSTABLE, "drift |u|^2 = %g must stay below c_s^2 = %g", u2, (double)lc->cs2);
   *tau_out = tau;
   return LKP_OK;
+}
+
+bool has_drift(const lkp_problem_desc *d) {
+  return d->drift[0] != 0.0 || d->drift[1] != 0.0 || d->drift[2] != 0.0;
 }
 
 lkp_status ensure_partials(lkp_handle *h, size_t nblocks) {
@@ -702,10 +715,22 @@ void stencil_weights(const lkp_handle *h, bool fp32, StencilParams *p) {
   orbit_weights(h, h->phi, fp32, p);
 }
 
-unsigned partial_blocks(const lkp_handle *h) {
-  const unsigned a = sweep_blocks(h, 4);
-  const unsigned b = stencil_blocks(h->lattice, (unsigned)h->n[0], (unsigned)h->n[1], (unsigned)h->n[2]);
+unsigned partial_blocks(int lattice, const int64_t n[3]) {
+  const unsigned ncells = (unsigned)(n[0] * n[1] * n[2]);
+  const unsigned a = (ncells + cells_per_block(4) - 1) / cells_per_block(4);
+  const unsigned b = stencil_blocks(lattice, (unsigned)n[0], (unsigned)n[1], (unsigned)n[2]);
   return std::max(a, b) + 8;
+}
+
+unsigned partial_blocks(const lkp_handle *h) { return partial_blocks(h->lattice, h->n); }
+
+// Device bytes of a stencil-form (omega = 1) handle: Phi twice, G, the FP64
+// source, norms; F32_IR adds four FP32 fields.
+int64_t scalar_footprint(int precision, int lattice, const int64_t n3[3]) {
+  const int64_t n = n3[0] * n3[1] * n3[2];
+  int64_t b = 8 * n * (precision == LKP_F32 ? 3 : 4) + (int64_t)partial_blocks(lattice, n3) * NUM_NORMS * 8 + 4096;
+  if (precision == LKP_F32_IR) b += 4 * 4 * n;
+  return b;
 }
 
 lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::vector<double> &S) {
@@ -724,8 +749,7 @@ lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::ve
   const size_t n = h->ncells;
   h->S_host = S;
   const int64_t nb = partial_blocks(h);
-  h->footprint = 8 * (int64_t)n * (h->precision == LKP_F32 ? 3 : 4) + nb * NUM_NORMS * 8 + 4096;
-  if (h->precision == LKP_F32_IR) h->footprint += 4 * 4 * (int64_t)n;
+  h->footprint = scalar_footprint(h->precision, h->lattice, h->n);
   HIP_TRY(hipMalloc(&h->norms_dev, NUM_NORMS * sizeof(double)));
   HIP_TRY(hipHostMalloc(&h->norms_host, NUM_NORMS * sizeof(double), hipHostMallocDefault));
   if (lkp_status st = ensure_partials(h, nb)) return st;
@@ -796,6 +820,19 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   std::vector<long double> phi, chi;
   if (!shape_coefficients(lc, d->order, &phi, &chi))
     return fail(LKP_ERR_LATTICE_ORDER, "no coefficients for order %d", d->order);
+  h->drift = has_drift(d);
+  if (h->drift) {
+    // advection-diffusion: the equilibrium of the Gaussian moved by u, to
+    // second order in u (first moment u, second moment c_s^2 delta + u u)
+    const long double c2 = lc.cs2;
+    long double u2 = 0;
+    for (int a = 0; a < 3; ++a) u2 += (long double)d->drift[a] * d->drift[a];
+    for (int i = 0; i < h->Q; ++i) {
+      long double vu = 0;
+      for (int a = 0; a < 3; ++a) vu += (long double)lc.table.v[i][a] * d->drift[a];
+      phi[i] += lc.w[i] * (vu / c2 + (vu * vu - c2 * u2) / (2 * c2 * c2));
+    }
+  }
   h->w.resize(h->Q);
   h->phi.resize(h->Q);
   h->chi.resize(h->Q);
@@ -833,8 +870,9 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   std::vector<double> S(n);
   for (size_t c = 0; c < n; ++c) S[c] = (remove ? s[c] - mean : s[c]) * scale;
 
-  // omega = 1 exactly: run the scalar stencil form unless populations are asked for
-  h->scalar = (h->omega == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP);
+  // omega = 1 exactly: run the scalar stencil form unless populations are asked
+  // for (or a drift makes phi_i differ within a velocity orbit)
+  h->scalar = (h->omega == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP) && !h->drift;
   if (h->scalar && h->bf16dev())
     return fail(LKP_ERR_UNSUPPORTED,
                 "BF16DEV_IR at tau_lb = 1: the stencil form keeps no populations (the deviation "
@@ -974,9 +1012,10 @@ int64_t lkp_footprint_bytes(const lkp_problem_desc *d) {
     lkp::rt::fail(LKP_OK, "%s", keep.c_str());
     return 0;
   }
-  const bool scalar = (1.0 / tau == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP);
+  const bool scalar = (1.0 / tau == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP) && !has_drift(d);
+  if (scalar) return scalar_footprint(d->precision, d->lattice, d->n);
   return footprint_of(d->precision, lc.table.q, d->n[0] * d->n[1] * d->n[2],
-                      (d->flags & LKP_FLAG_IN_PLACE) && !scalar);
+                      (d->flags & LKP_FLAG_IN_PLACE) != 0);
 }
 
 lkp_status lkp_create(const lkp_problem_desc *d, lkp_handle **out) {
@@ -1408,6 +1447,16 @@ lkp_status lkp_lattice_info(int32_t lattice, int32_t order, int32_t *Q, int32_t 
     if (phi) phi[i] = (double)ph[i];
     if (chi) chi[i] = (double)ch[i];
   }
+  return LKP_OK;
+}
+
+lkp_status lkp_get_coefficients(lkp_handle *h, double *phi, double *chi) {
+  if (!h) return fail(LKP_ERR_ARG, "lkp_get_coefficients: null handle");
+  for (int i = 0; i < h->Q; ++i) {
+    if (phi) phi[i] = h->phi[i];
+    if (chi) chi[i] = h->chi[i];
+  }
+  clear_error();
   return LKP_OK;
 }
 

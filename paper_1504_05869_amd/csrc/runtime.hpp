@@ -68,6 +68,7 @@ struct lkp_handle {
   unsigned ncells = 0;
   double tau_lb = 0, omega = 0, cs2 = 0;
   std::vector<double> w, phi, chi;
+  bool drift = false;       // advection-diffusion handle (nonzero drift in phi_i)
   std::vector<double> c64;  // [omega phi_i]_Q, [chi_i]_Q (FP64 sweeps, residual)
   std::vector<float> c32;   // the same rounded to FP32 (FP32 and IR inner sweeps)
   hipStream_t stream = nullptr;

@@ -133,3 +133,39 @@ def test_in_place_halves_population_footprint():
         assert a - b == per * 111 * 64 ** 3
     big = lkp.footprint_bytes((512, 512, 512), "D3Q111", 5, knudsen=0.3, precision="f32_ir", in_place=True)
     assert big < 288e9 < lkp.footprint_bytes((512, 512, 512), "D3Q111", 5, knudsen=0.3, precision="f32_ir")
+
+
+def _drift_status(u, **kw):
+    s = np.zeros((16, 16))
+    d = _desc(shape=s.shape, **kw)
+    d.source = s.ctypes.data
+    for a, x in enumerate(u):
+        d.drift[a] = x
+    h = ctypes.c_void_p()
+    st = _lib.load().lkp_create(ctypes.byref(d), ctypes.byref(h))
+    msg = _lib.load().lkp_last_error().decode()
+    if h.value:
+        _lib.load().lkp_destroy(h)
+    return _lib.STATUS[st], msg
+
+
+def test_create_rejects_bad_drift():
+    """Drift components beyond the dimension, non-finite drift and
+    |u|^2 >= c_s^2 are refused before any device work."""
+    assert _drift_status((0.1, 0.0, 0.2))[0] == "LKP_ERR_ARG"
+    assert _drift_status((float("nan"), 0.0))[0] == "LKP_ERR_ARG"
+    st, msg = _drift_status((0.6, 0.5))          # D2Q25 c_s^2 ~ 0.37
+    assert st == "LKP_ERR_UNSTABLE" and "drift" in msg
+
+
+def test_drift_keeps_the_footprint_and_forces_the_population_form():
+    """A drifted handle at tau_lb = 1 keeps populations (the stencil form
+    shares phi_i within velocity orbits, which a drift breaks): its footprint
+    is the population one."""
+    d0 = _desc(tau_lb=1.0)
+    d1 = _desc(tau_lb=1.0)
+    d1.drift[0] = 0.05
+    d2 = _desc(tau_lb=1.3)
+    lib = _lib.load()
+    f0, f1, f2 = (lib.lkp_footprint_bytes(ctypes.byref(d)) for d in (d0, d1, d2))
+    assert f1 == f2 and f0 != f1
