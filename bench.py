@@ -43,10 +43,10 @@ def r_q(lkp, lattice: str) -> int:
 
 
 def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=None,
-               sweeps=200, chunks=1, population_sweep=False, in_place=False):
+               sweeps=200, chunks=1, population_sweep=False, in_place=False, drift=None):
     """Average duration of one sweep (HIP events on the solver's stream)."""
     with lkp.Problem(s, lattice, order, knudsen=knudsen, tau_lb=tau_lb, precision=precision,
-                     population_sweep=population_sweep, in_place=in_place) as p:
+                     population_sweep=population_sweep, in_place=in_place, drift=drift) as p:
         p.step(2)
         p.sync()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -359,6 +359,25 @@ def main():
                             "sweeps": rep["sweeps"], "outer": rep["outer"],
                             "est_rel_err": rep["est_rel_err"]})
         out["time_to_solution"] = tts
+        # advection-diffusion variant on the headline grid: drift u = (0.05, 0.02)
+        # (Peclet number |u| L / D ~ 0.6 at Kn = 0.1), rate and time to 1e-6
+        u = (0.05, 0.02)
+        adv = []
+        for prec in ("f64", "f32"):
+            r = sweep_rate(lkp, torch, s, lattice, order, prec, knudsen=kn, sweeps=200, drift=u)
+            r.update(form="advection-diffusion", drift=u)
+            adv.append({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()})
+        for prec in ("f64", "f32_ir"):
+            with lkp.Problem(s, lattice, order, knudsen=kn, precision=prec, drift=u) as q:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                rep = q.solve(tol_rel_l2=1e-6, check_every=100, max_sweeps=2_000_000)
+                torch.cuda.synchronize()
+                adv.append({"precision": prec, "tol_rel_l2": 1e-6, "drift": u,
+                            "seconds": round(time.perf_counter() - t1, 4),
+                            "sweeps": rep["sweeps"], "outer": rep["outer"],
+                            "est_rel_err": rep["est_rel_err"]})
+        out["advection_diffusion"] = adv
 
     if (not args.no_extras or args.serving_only) and not args.no_serving:
         out["serving"] = serving_run(args.serve_requests, args.serve_rate)
