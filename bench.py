@@ -155,22 +155,37 @@ def stiff_512(lkp, torch, tol: float, chunk: int, minutes: float) -> dict:
     return out
 
 
-def serving_run(n_requests: int, rate: float) -> dict:
-    """Scaled serving stream: continuous batching (FP32 + refinement) against
-    the same trace solved one at a time in FP64, both to estimated rel-L2 1e-6."""
+def serving_run(n_requests: int, rate: float, full_sizes: bool = False) -> dict:
+    """Serving stream: continuous batching (FP32 + refinement) against the same
+    trace solved one at a time in FP64, both to estimated rel-L2 1e-6.  The
+    default size mix is scaled down so that the run takes seconds; full_sizes
+    draws from {128..2048}^2 and {64,128,256}^3 with a 240 GiB HBM budget."""
     from paper_1504_05869_amd import serve
-    reqs = serve.make_stream(n_requests, rate=rate, seed=2024,
-                             sizes2d=((64, 64), (128, 128), (256, 256), (512, 512)),
-                             sizes3d=((32, 32, 32), (48, 48, 48), (64, 64, 64)))
-    srv = serve.Server(serve.GpuBackend("f32_ir"), hbm_budget=64 << 30, sweeps_per_tick=50,
-                       tol=1e-6)
+    if full_sizes:
+        s2 = tuple((n, n) for n in (128, 256, 512, 1024, 2048))
+        s3 = tuple((n, n, n) for n in (64, 128, 256))
+        budget = 240 << 30
+    else:
+        s2 = ((64, 64), (128, 128), (256, 256), (512, 512))
+        s3 = ((32, 32, 32), (48, 48, 48), (64, 64, 64))
+        budget = 64 << 30
+    reqs = serve.make_stream(n_requests, rate=rate, seed=2024, sizes2d=s2, sizes3d=s3)
+
+    def say(msg):
+        if full_sizes:
+            print(f"[serving] {msg}", file=sys.stderr, flush=True)
+
+    srv = serve.Server(serve.GpuBackend("f32_ir"), hbm_budget=budget, sweeps_per_tick=50,
+                       tol=1e-6, progress=say)
     res, summ = srv.run(reqs)
-    base, bsum = serve.run_one_at_a_time(reqs, "f64", tol=1e-6, check_every=50)
+    base, bsum = serve.run_one_at_a_time(reqs, "f64", tol=1e-6, check_every=50, progress=say)
     keys = ("completed", "problems_per_s", "p50_latency_s", "p99_latency_s", "makespan_s",
             "sweeps_total")
+    sizes = ("{128,256,512,1024,2048}^2 and 3D D3Q111 N=5 {64,128,256}^3" if full_sizes else
+             "{64,128,256,512}^2 and 3D D3Q111 N=5 {32,48,64}^3")
     return {"stream": f"{n_requests} requests, Poisson arrivals at {rate}/s, 2D D2Q81 N=5 "
-                      "{64,128,256,512}^2 and 3D D3Q111 N=5 {32,48,64}^3, Kn~U(0.05,0.5), "
-                      "Gaussian blobs, retire at estimated rel-L2 1e-6",
+                      f"{sizes}, Kn~U(0.05,0.5), Gaussian blobs, retire at estimated rel-L2 1e-6",
+            "hbm_budget_bytes": budget,
             "batched_f32_ir": {k: summ[k] for k in keys}
                               | {k: summ[k] for k in ("ticks", "graph_captures", "graph_replays")
                                  if k in summ},
@@ -193,6 +208,8 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution runs")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-sizes", choices=("scaled", "full"), default="scaled",
+                    help="serving size mix: scaled (seconds) or full (up to 2048^2 and 256^3)")
     ap.add_argument("--c5", action="store_true",
                     help="only the 512^3 stiff workload: FP32+IR in place vs FP64 (long)")
     ap.add_argument("--c5-tol", type=float, default=1e-10)
@@ -380,7 +397,8 @@ def main():
         out["advection_diffusion"] = adv
 
     if (not args.no_extras or args.serving_only) and not args.no_serving:
-        out["serving"] = serving_run(args.serve_requests, args.serve_rate)
+        out["serving"] = serving_run(args.serve_requests, args.serve_rate,
+                                     full_sizes=args.serve_sizes == "full")
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, lattice, order, info["tau_lb"], args.cpu_seconds)

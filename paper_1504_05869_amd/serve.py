@@ -134,7 +134,9 @@ class Server:
     """Admission by footprint, batched ticks, retirement at tolerance."""
 
     def __init__(self, backend, hbm_budget: int, sweeps_per_tick: int = 50, tol: float = 1e-6,
-                 max_sweeps: int = 2_000_000, clock=time.perf_counter, sleep=time.sleep):
+                 max_sweeps: int = 2_000_000, clock=time.perf_counter, sleep=time.sleep,
+                 progress=None):
+        self.progress = progress   # optional callable(str), called at each retirement
         self.backend = backend
         self.budget = int(hbm_budget)
         self.K = int(sweeps_per_tick)
@@ -190,6 +192,9 @@ class Server:
                 res.phi = self.backend.retire(p)
                 res.finished = self.clock() - t0
                 used -= fp
+                if self.progress:
+                    self.progress(f"retired request {req.rid} {req.shape} {res.status} "
+                                  f"sweeps {res.sweeps} at {res.finished:.2f} s")
         out = [results[r.rid] for r in reqs]
         extra = {"ticks": self.ticks, "peak_hbm_bytes": self.peak_used, "hbm_budget": self.budget}
         stats = getattr(self.backend, "graph_stats", None)
@@ -200,7 +205,7 @@ class Server:
 
 def run_one_at_a_time(requests: list[Request], precision: str = "f64", tol: float = 1e-6,
                       check_every: int = 50, keep_phi: bool = False, clock=time.perf_counter,
-                      sleep=time.sleep) -> tuple[list[Result], dict]:
+                      sleep=time.sleep, progress=None) -> tuple[list[Result], dict]:
     """Baseline: the same trace solved one request at a time (lkp_solve)."""
     import paper_1504_05869_amd as lkp
     from . import workloads as W
@@ -221,6 +226,9 @@ def run_one_at_a_time(requests: list[Request], precision: str = "f64", tol: floa
                 res.phi = p.phi_host()
         res.finished = clock() - t0
         out.append(res)
+        if progress:
+            progress(f"solved request {req.rid} {req.shape} {res.status} sweeps {res.sweeps} "
+                     f"at {res.finished:.2f} s")
     return out, summarize(out)
 
 
