@@ -23,6 +23,11 @@ path:
 * ``dense``    -- the same fixed point by a dense linear solve on tiny grids.
 * ``bf16dev``  -- the same sweep with the post-collision state stored as an
   FP32 moment and BF16 deviations (storage-precision ablation).
+* ``generator`` -- the search for new velocity sets from the quadrature
+  conditions (Sec. 3), with positive weights and a von Neumann stability
+  filter.
+* ``drift``    -- the advection-diffusion variant (the equilibrium of a
+  Gaussian moved by a uniform drift) and its exact complex fixed point.
 
 Every function with no independent pin says "parity unpinned" in its
 docstring; at present there is none.
