@@ -143,3 +143,71 @@ def test_group_rejects_drifted_handle():
                 g.add(p, tol_rel_l2=1e-8)
     finally:
         g.close()
+
+
+def test_drifted_bf16_deviation_sweeps_match_emulation():
+    """BF16 deviation storage with a drifted equilibrium: the plain deviation
+    sweeps agree with the oracle's FP32 emulation of the same storage."""
+    from oracle import bf16dev as B
+    lattice, order, tau, shape, u = "D2Q81", 5, 2.5, (50, 70), (0.05, -0.03)
+    s = W.zero_mean(np.random.default_rng(11).standard_normal(shape))
+    K = 9
+    with lkp.Problem(s, lattice, order, tau_lb=tau, precision="bf16dev_ir", drift=u) as p:
+        p.step(K)
+        a = p.phi_host()
+    prob = SW.Problem(lattice, order, tau, s, drift=u)
+    emu, _ = B.run(prob, K, S=prob.S.astype(np.float32), fp32_groups=1)
+    exact, _ = SW.run(prob, K)
+    say("bf16dev drift: identical", float(np.mean(a == emu)), "vs emulation", rel_l2(a, emu),
+        "BF16 effect", rel_l2(emu, exact))
+    assert float(np.mean(a == emu)) >= 0.999
+    assert rel_l2(a, emu) <= 1e-6 * rel_l2(emu, exact) + 1e-12
+
+
+def test_drifted_bf16_refinement_reaches_fixed_point():
+    lattice, order, shape, u = "D2Q81", 5, (48, 40), (0.05, -0.03)
+    s = W.zero_mean(W.gaussian_blobs(shape, 5, 1.5, 3))
+    tau = 2.0
+    with lkp.Problem(s, lattice, order, tau_lb=tau, precision="bf16dev_ir", drift=u) as p:
+        rep = p.solve(tol_rel_l2=1e-9, check_every=20, max_sweeps=400000)
+        phi = p.phi_host()
+    err = rel_l2(phi, DR.fixed_point(lattice, order, tau, s, u))
+    say("bf16dev drift solve: sweeps", rep["sweeps"], "outer", rep["outer"], "true err", err)
+    assert err <= 1e-8
+
+
+def test_drifted_in_place_refinement_equals_pull_bitwise():
+    """FP32 + refinement with a drift, in place and with two buffers: the same
+    answer bit for bit (the in-place layouts change only where values live)."""
+    import os
+    order, shape, u = 5, (40, 36), (0.05, -0.03)
+    s = W.zero_mean(W.gaussian_blobs(shape, 5, 1.5, 9))
+    old = os.environ.get("LKP_AUTOTUNE")
+    os.environ["LKP_AUTOTUNE"] = "0"
+    try:
+        out = []
+        for ip in (False, True):
+            with lkp.Problem(s, "D2Q81", order, tau_lb=2.0, precision="f32_ir", drift=u,
+                             in_place=ip) as p:
+                rep = p.solve(tol_rel_l2=1e-10, check_every=50, max_sweeps=400000)
+                out.append((p.phi_host(), rep["sweeps"]))
+    finally:
+        if old is None:
+            os.environ.pop("LKP_AUTOTUNE")
+        else:
+            os.environ["LKP_AUTOTUNE"] = old
+    assert out[0][1] == out[1][1] and np.array_equal(out[0][0], out[1][0])
+
+
+def test_set_equilibrium_in_place_matches_two_buffers():
+    order, u = 5, (0.05, 0.03)
+    shape = (24, 32)
+    phi0 = np.random.default_rng(6).standard_normal(shape)
+    out = []
+    for ip in (False, True):
+        with lkp.Problem(np.zeros(shape), "D2Q81", order, tau_lb=1.3, drift=u,
+                         population_sweep=True, in_place=ip) as p:
+            p.set_equilibrium(phi0)
+            p.step(12)
+            out.append(p.phi_host())
+    assert np.array_equal(out[0], out[1])
