@@ -169,3 +169,22 @@ def test_drift_keeps_the_footprint_and_forces_the_population_form():
     lib = _lib.load()
     f0, f1, f2 = (lib.lkp_footprint_bytes(ctypes.byref(d)) for d in (d0, d1, d2))
     assert f1 == f2 and f0 != f1
+
+
+def test_grid_limits_empty_and_oversize():
+    """An axis of 0 cells and grids of 2^29 cells or more are refused (a
+    population plane must stay below 4 GiB in FP64); the largest grid below
+    the limit is accepted by the footprint query."""
+    lib = _lib.load()
+    assert _create_status(np.zeros((0, 16)))[0] == "LKP_ERR_ARG"
+    for shape, ok in [((16384, 32768), False), ((16383, 32768), True)]:
+        d = _desc(shape=shape, lattice="D2Q9", order=3, tau_lb=1.3)
+        fp = lib.lkp_footprint_bytes(ctypes.byref(d))
+        assert (fp > 0) == ok
+        if not ok:  # lkp_create refuses it before reading the source
+            tiny = np.zeros(4)
+            d.source = tiny.ctypes.data
+            h = ctypes.c_void_p()
+            st = lib.lkp_create(ctypes.byref(d), ctypes.byref(h))
+            assert _lib.STATUS[st] == "LKP_ERR_ARG" and not h.value
+            assert "too large" in lib.lkp_last_error().decode()

@@ -357,3 +357,18 @@ def test_full_size_256cubed_d3q111_stencil(precision):
         round(t1 - t0, 2), "est", rep["est_rel_err"], "sampled residual", res)
     assert rep["est_rel_err"] <= 1e-11
     assert res <= 1e-11
+
+
+@pytest.mark.parametrize("precision,tau", [("f64", 1.5), ("f32", 1.5), ("f32_ir", 1.5),
+                                           ("bf16dev_ir", 1.5), ("f64", 1.0), ("f32_ir", 1.0)])
+def test_zero_source_converges_to_zero(precision, tau):
+    """Degenerate input: s = 0.  Every precision and form (tau_lb = 1 is the
+    stencil form) reports convergence with Phi = 0 instead of dividing by the
+    zero norm."""
+    s = np.zeros((24, 20))
+    with lkp.Problem(s, "D2Q81", 5, tau_lb=tau, precision=precision) as p:
+        rep = p.solve(tol_rel_l2=1e-10, check_every=20, max_sweeps=1000)
+        phi = p.phi_host()
+    say("zero source", precision, tau, rep["status"], rep["sweeps"], rep["est_rel_err"])
+    assert rep["status"] == 0
+    assert np.all(phi == 0.0)
