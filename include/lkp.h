@@ -234,10 +234,18 @@ lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info);
 /* The handle's equilibrium and source shapes phi_i, chi_i (Sec. 3, Eqs.
  * omega:eq, chi:eq, omega:eq3, chi:eq3, with the drift terms of a drifted
  * handle) in the order of lkp_lattice_info's velocities: Q FP64 values each
- * into host arrays (either may be NULL).  A time-dependent run starts from an
- * equilibrium state by lkp_set_populations with f*_i = phi_i Phi_0 and then
- * advances with lkp_step.  Errors: LKP_ERR_ARG. */
+ * into host arrays (either may be NULL).  Errors: LKP_ERR_ARG. */
 lkp_status lkp_get_coefficients(lkp_handle *h, double *phi, double *chi);
+
+/* Time-dependent use (the sweep as a time step of the diffusion or
+ * advection-diffusion equation, Sec. 2 and 5): set the post-collision state
+ * to the equilibrium f*_i = phi_i Phi_0 of the field Phi_0 (n FP64 values,
+ * host or device, caller-owned), computed on the device in the handle's
+ * layout and precision; then advance with lkp_step and read lkp_get_phi.
+ * Allocates Q*n*8 + n*8 bytes of temporary device memory for the call.
+ * Errors: LKP_ERR_ARG, LKP_ERR_UNSUPPORTED (tau_lb = 1 stencil form),
+ * LKP_ERR_OOM, LKP_ERR_HIP. */
+lkp_status lkp_set_equilibrium(lkp_handle *h, const double *phi0, int32_t phi0_is_device);
 
 /* Wait for all of the handle's queued work. */
 lkp_status lkp_sync(lkp_handle *h);

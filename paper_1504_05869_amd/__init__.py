@@ -209,10 +209,18 @@ class Problem:
         return phi, chi
 
     def set_equilibrium(self, phi0) -> None:
-        """Start a time-dependent run from the equilibrium f*_i = phi_i Phi_0."""
-        phi, _ = self.coefficients()
-        phi0 = np.asarray(phi0, dtype=np.float64)
-        self.set_populations(phi.reshape((-1,) + (1,) * phi0.ndim) * phi0[None])
+        """Start a time-dependent run from the equilibrium f*_i = phi_i Phi_0
+        (formed on the device by the library)."""
+        if isinstance(phi0, torch.Tensor) and phi0.is_cuda:
+            t = phi0.detach().to(torch.float64).contiguous()
+            if tuple(t.shape) != self.shape:
+                raise ValueError("Phi_0 must have the problem's shape")
+            check(self._lib.lkp_set_equilibrium(self._h, t.data_ptr(), 1), "lkp_set_equilibrium")
+            return
+        a = np.ascontiguousarray(phi0, dtype=np.float64)
+        if a.shape != self.shape:
+            raise ValueError("Phi_0 must have the problem's shape")
+        check(self._lib.lkp_set_equilibrium(self._h, a.ctypes.data, 0), "lkp_set_equilibrium")
 
     def info(self) -> dict:
         i = _lib.HandleInfo()

@@ -19,7 +19,8 @@ STATUS = {0: "LKP_OK", 1: "LKP_ERR_ARG", 2: "LKP_ERR_LATTICE_ORDER", 3: "LKP_ERR
           10: "LKP_ERR_UNSUPPORTED"}
 EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_solve", "lkp_step",
            "lkp_residual", "lkp_get_phi", "lkp_get_populations", "lkp_set_populations",
-           "lkp_lattice_info", "lkp_get_info", "lkp_get_coefficients", "lkp_sync", "lkp_last_error",
+           "lkp_lattice_info", "lkp_get_info", "lkp_get_coefficients", "lkp_set_equilibrium",
+           "lkp_sync", "lkp_last_error",
            "lkp_group_create", "lkp_group_add", "lkp_group_remove", "lkp_group_step",
            "lkp_group_destroy", "lkp_group_graph_stats"]
 MEMBER_STATES = {0: "running", 1: "converged", 2: "failed"}
@@ -106,6 +107,7 @@ def load() -> ctypes.CDLL:
                                             ctypes.c_void_p, P(ctypes.c_double)]),
         "lkp_get_info": (ctypes.c_int, [H, P(HandleInfo)]),
         "lkp_get_coefficients": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_void_p]),
+        "lkp_set_equilibrium": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_int32]),
         "lkp_sync": (ctypes.c_int, [H]),
         "lkp_last_error": (ctypes.c_char_p, []),
         "lkp_group_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,

@@ -183,6 +183,10 @@ hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, 
 
 // Elementwise helpers.
 hipError_t launch_f64_to_f32(const double *in, float *out, size_t n, hipStream_t s);
+
+// out[i n + x] = coef[i] phi0[x] for q planes of n cells (device pointers).
+hipError_t launch_equilibrium(const double *phi0, const double *coef, double *out, size_t n, int q,
+                              hipStream_t s);
 hipError_t launch_f32_to_f64(const float *in, double *out, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);

@@ -1428,6 +1428,38 @@ lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_
   return LKP_OK;
 }
 
+lkp_status lkp_set_equilibrium(lkp_handle *h, const double *phi0, int32_t phi0_is_device) {
+  if (!h || !phi0) return fail(LKP_ERR_ARG, "lkp_set_equilibrium: null argument");
+  if (h->scalar)
+    return fail(LKP_ERR_UNSUPPORTED, "the tau_lb = 1 stencil form keeps Phi only; create the handle "
+                                     "with LKP_FLAG_POPULATION_SWEEP to start from an equilibrium");
+  const size_t n = h->ncells, QN = (size_t)h->Q * n;
+  double *p0 = nullptr, *coef = nullptr, *f = nullptr;
+  auto release_tmp = [&]() {
+    if (p0) (void)hipFree(p0);
+    if (coef) (void)hipFree(coef);
+    if (f) (void)hipFree(f);
+  };
+  hipError_t e = hipMalloc(&p0, n * 8);
+  if (e == hipSuccess) e = hipMalloc(&coef, (size_t)h->Q * 8);
+  if (e == hipSuccess) e = hipMalloc(&f, QN * 8);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p0, phi0, n * 8, phi0_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(coef, h->phi.data(), (size_t)h->Q * 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = launch_equilibrium(p0, coef, f, n, h->Q, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    release_tmp();
+    return fail(e == hipErrorOutOfMemory ? LKP_ERR_OOM : LKP_ERR_HIP, "lkp_set_equilibrium: %s",
+                hipGetErrorString(e));
+  }
+  const lkp_status st = lkp_set_populations(h, f, 1);
+  release_tmp();
+  return st;
+}
+
 lkp_status lkp_lattice_info(int32_t lattice, int32_t order, int32_t *Q, int32_t *dim, int32_t *v,
                             double *w, double *phi, double *chi, double *cs2) {
   if (lattice < 0 || lattice >= LKP_NUM_LATTICES) return fail(LKP_ERR_ARG, "unknown lattice");

@@ -29,6 +29,14 @@ __global__ void k_f64_to_f32(const double *__restrict__ in, float *__restrict__ 
     out[i] = (float)in[i];
 }
 
+// f_i(x) = phi_i Phi_0(x) for every velocity plane i (grid-stride over Q n values)
+__global__ void k_equilibrium(const double *__restrict__ phi0, const double *__restrict__ coef,
+                              double *__restrict__ out, size_t n, size_t qn) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < qn;
+       k += (size_t)gridDim.x * blockDim.x)
+    out[k] = coef[k / n] * phi0[k % n];
+}
+
 __global__ void k_f32_to_f64(const float *__restrict__ in, double *__restrict__ out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -149,6 +157,13 @@ hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, 
 
 hipError_t launch_f64_to_f32(const double *in, float *out, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_equilibrium(const double *phi0, const double *coef, double *out, size_t n, int q,
+                              hipStream_t s) {
+  const size_t qn = n * (size_t)q;
+  hipLaunchKernelGGL(k_equilibrium, dim3(grid_for(qn)), dim3(256), 0, s, phi0, coef, out, n, qn);
   return hipGetLastError();
 }
 

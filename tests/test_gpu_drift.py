@@ -211,3 +211,38 @@ def test_set_equilibrium_in_place_matches_two_buffers():
             p.step(12)
             out.append(p.phi_host())
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_ir"])
+@pytest.mark.parametrize("in_place", [False, True])
+def test_set_equilibrium_equals_host_built_populations(precision, in_place):
+    """lkp_set_equilibrium (f*_i = phi_i Phi_0 formed on the device) stores
+    exactly what lkp_set_populations stores for the same values built on the
+    host from the handle's coefficients."""
+    shape, u = (24, 32), (0.05, 0.03)
+    phi0 = np.random.default_rng(8).standard_normal(shape)
+    out = []
+    for dev in (True, False):
+        with lkp.Problem(np.zeros(shape), "D2Q81", 5, tau_lb=1.3, drift=u, precision=precision,
+                         population_sweep=True, in_place=in_place) as p:
+            if dev:
+                p.set_equilibrium(phi0)
+            else:
+                c, _ = p.coefficients()
+                p.set_populations(c[:, None, None] * phi0[None])
+            f0 = p.populations()
+            if precision == "f32_ir":  # refinement handles are driven by lkp_solve only
+                out.append((f0, None))
+                continue
+            p.step(6)
+            out.append((f0, p.phi_host()))
+    assert np.array_equal(out[0][0], out[1][0])
+    if out[0][1] is not None:
+        assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_set_equilibrium_refused_by_stencil_form():
+    with lkp.Problem(np.zeros((16, 16)), "D2Q81", 5, tau_lb=1.0) as p:
+        with pytest.raises(lkp.LkpError) as ei:
+            p.set_equilibrium(np.ones((16, 16)))
+        assert ei.value.name == "LKP_ERR_UNSUPPORTED"
