@@ -106,3 +106,25 @@ def test_planted_wrong_gaussian_moment_finds_nothing(monkeypatch):
         return m * t ** (sum(e) // 2)
     monkeypatch.setattr(G, "gauss_moment", wrong)
     assert G.solve_subset(L.GENERATED_SHELLS["D2Q37"], G.classes(2, 8)) == []
+
+
+# 22 shells (components up to 6) found by a randomized search over shell subsets
+SHELLS_3D_DEG12 = [(0, 0, 0), (1, 1, 1), (2, 2, 2), (6, 1, 1), (3, 3, 3), (3, 0, 0), (4, 1, 1),
+                   (6, 0, 0), (5, 3, 1), (6, 3, 2), (2, 2, 0), (5, 1, 1), (3, 1, 1), (5, 5, 5),
+                   (6, 5, 2), (3, 1, 0), (4, 3, 0), (4, 3, 2), (3, 2, 1), (6, 3, 0), (4, 2, 0),
+                   (2, 0, 0)]
+
+
+def test_3d_degree12_set_exists_but_order7_grows():
+    """A cubic set exact for every monomial of degree <= 13 (the N = 7
+    conditions) with positive weights: 495 velocities, one admissible c_s^2.
+    Its N = 7 scheme has a growing mode (unlike N = 5 on the same set)."""
+    sols = G.solve_subset(SHELLS_3D_DEG12, G.classes(3, 12))
+    assert len(sols) == 1
+    t, W = sols[0]
+    assert all(w > 0 for w in W)
+    f = G.Found(3, 12, SHELLS_3D_DEG12, t, W, sum(len(G.orbit(r)) for r in SHELLS_3D_DEG12))
+    assert f.q == 495
+    assert abs(float(t) - 2.18400454768877) < 1e-12
+    assert G.spectral_radius(f, 7, 1.0, nk=4) > 1.03
+    assert G.spectral_radius(f, 5, 1.0, nk=4) <= 1.0 + 1e-9
