@@ -88,6 +88,21 @@ def measured_traffic(tag: str):
     return int(round(rec["traffic_bytes"]))
 
 
+def paper_context(eps=1e-3):
+    """The paper's own comparison of orders, quoted as context: time to error
+    eps from its 1D fits (Table 1: throughput xi_N, steps scale b_N, error
+    fit a_N L^-alpha_N) through Eq. TEPS, t_N = (b_N / xi_N) (a_N / eps)^(3 / alpha_N),
+    on hardware the paper does not state."""
+    fits = {1: (26.2e6, 10.98, 1.645, 1), 3: (21.4e6, 10.98, 1.645, 1),
+            5: (5.44e6, 5.46, 33.11, 3), 7: (5.76e6, 3.23, 992.3, 5)}
+    t = {n: b / xi * (a / eps) ** (3.0 / al) for n, (xi, b, a, al) in fits.items()}
+    return {"what": "standard LB (N=1) vs higher order, time to error 1e-3 in 1D, from the "
+                    "paper's Table 1 fits and Eq. TEPS (hardware and precision unstated; context "
+                    "only, not a measurement here)",
+            "seconds_by_order": {str(n): float(f"{v:.4g}") for n, v in t.items()},
+            "speedup_N1_over_N7": float(f"{t[1] / t[7]:.3g}")}
+
+
 def cpu_baseline(s, lattice, order, tau, seconds=15.0):
     """Oracle C sweep (FP64, OpenMP) on the same grid for a bounded time."""
     from oracle import sweep as SW
@@ -302,6 +317,7 @@ def main():
                      "traffic": measured_traffic("k_sweep_d2q81_f64_1024x1024"),
                      "kernel": "k_sweep (D2Q81, FP64)",
                      "bytes_per_launch": n * bpc, "ms_per_launch": round(ms_sweep, 5)},
+        "paper_context": paper_context(),
         "last_check": {"est_rel_err": last["est_rel_err"], "rate": last["rate"]},
     }
 
