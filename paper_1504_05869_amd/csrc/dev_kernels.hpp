@@ -35,7 +35,11 @@ struct DevParams {
 static_assert(sizeof(DevParams) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // Velocity-group split of the deviation sweep (one variant per lattice).
-constexpr int dev_split(int lattice) { return velocity_table(lattice).q >= 169 ? 4 : 1; }
+// Measured on D2Q81 at 1024^2: P = 2 runs 2.4x faster than P = 1 (81 values
+// per lane limit the waves in flight) and 1.6x faster than P = 4.
+constexpr int dev_split(int lattice) {
+  return velocity_table(lattice).q >= 169 ? 4 : (velocity_table(lattice).q >= 37 ? 2 : 1);
+}
 
 // Blocks of one deviation sweep over ncells cells.
 constexpr unsigned dev_blocks(int lattice, unsigned ncells) {

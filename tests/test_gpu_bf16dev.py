@@ -23,8 +23,8 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-# velocity groups of the deviation sweep: 4 for 169 velocities, else 1
-GROUPS = {"D2Q169": 4}
+# velocity groups of the deviation sweep: 4 for 169 velocities, 2 from 37, else 1
+GROUPS = {"D2Q169": 4, "D2Q81": 2, "D3Q111": 2, "D2Q37": 2, "D2Q77": 2}
 
 
 @pytest.mark.parametrize("lattice,order,tau,shape", [

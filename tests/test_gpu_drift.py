@@ -156,7 +156,7 @@ def test_drifted_bf16_deviation_sweeps_match_emulation():
         p.step(K)
         a = p.phi_host()
     prob = SW.Problem(lattice, order, tau, s, drift=u)
-    emu, _ = B.run(prob, K, S=prob.S.astype(np.float32), fp32_groups=1)
+    emu, _ = B.run(prob, K, S=prob.S.astype(np.float32), fp32_groups=2)  # D2Q81 split
     exact, _ = SW.run(prob, K)
     say("bf16dev drift: identical", float(np.mean(a == emu)), "vs emulation", rel_l2(a, emu),
         "BF16 effect", rel_l2(emu, exact))
