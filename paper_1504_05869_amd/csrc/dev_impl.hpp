@@ -75,6 +75,10 @@ __global__ void __launch_bounds__(256) k_sweep_dev(DevParams p) {
   const size_t plane = p.plane;
 
   float f[QG];
+  // correction sweeps: the population source r_i, loaded with the pulled
+  // values so that its loads overlap theirs instead of waiting one by one
+  // after the moment (used unchanged in the store phase)
+  float rs[INNER ? QG : 1];
   double part = 0.0;
   auto load_group = [&](auto Gc) {
     constexpr int G = decltype(Gc)::value;
@@ -86,6 +90,7 @@ __global__ void __launch_bounds__(256) k_sweep_dev(DevParams p) {
       const unsigned off = (zw[vz + VMZ] * p.ny + yw[vy + VMY]) * p.nx + xw[vx + VMX];
       const float nb = bf16_to_f32(p.nin[(size_t)i * plane + off]);
       f[i - lo] = p.phi[i] * p.phin[off] + nb;
+      if constexpr (INNER) rs[i - lo] = p.src[(size_t)i * plane + cc];
     });
     static_for<lo, hi>([&](auto I) { part += (double)f[(int)I - lo]; });
   };
@@ -119,7 +124,7 @@ __global__ void __launch_bounds__(256) k_sweep_dev(DevParams p) {
     static_for<lo, hi>([&](auto I) {
       constexpr int i = decltype(I)::value;
       float s;
-      if constexpr (INNER) s = p.src[(size_t)i * plane + cc];
+      if constexpr (INNER) s = rs[i - lo];
       else s = p.chi[i] * S;
       const float nn = p.om1 * (f[i - lo] - p.phi[i] * Ph) + s;
       if (valid) p.nout[(size_t)i * plane + c] = f32_to_bf16(nn);
