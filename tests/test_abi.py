@@ -188,3 +188,14 @@ def test_grid_limits_empty_and_oversize():
             st = lib.lkp_create(ctypes.byref(d), ctypes.byref(h))
             assert _lib.STATUS[st] == "LKP_ERR_ARG" and not h.value
             assert "too large" in lib.lkp_last_error().decode()
+
+
+def test_new_entry_points_reject_null_arguments():
+    """Host-side argument checks of the coefficient query, the equilibrium
+    initial state and the group graph counters (no device work)."""
+    lib = _lib.load()
+    buf = np.zeros(4)
+    assert _lib.STATUS[lib.lkp_get_coefficients(None, buf.ctypes.data, None)] == "LKP_ERR_ARG"
+    assert _lib.STATUS[lib.lkp_set_equilibrium(None, buf.ctypes.data, 0)] == "LKP_ERR_ARG"
+    c = ctypes.c_int64()
+    assert _lib.STATUS[lib.lkp_group_graph_stats(None, ctypes.byref(c), None)] == "LKP_ERR_ARG"
