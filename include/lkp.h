@@ -6,7 +6,7 @@
  * is solved as the steady state of the diffusion equation with source
  * (Sec. 2, Eq. DIFFU), itself the small-Knudsen limit of a BGK kinetic equation
  * (Eq. boltzmann).  On a lattice of Q discrete velocities v_i each sweep does,
- * for every cell x (Sec. 3 and 4):
+ * for every cell x (Sec. 4 and 5):
  *
  *     stream (pull):    f_i(x)    = f*_i(x - v_i)              (periodic)
  *     moment:           Phi(x)    = sum_i f_i(x)
@@ -15,7 +15,7 @@
  * with omega = 1 / tau_lb, the separable equilibrium phi(v) Phi (Eq. equilibrium2)
  * and source chi(v) S whose Hermite coefficients cancel the unwanted moments up
  * to order N (Eq. CON; Eqs. omega:eq, chi:eq, omega:eq3, chi:eq3), and the
- * strong source S = s c_s^2 (tau_lb - 1/2) (Sec. 4).  The answer is Phi at the
+ * strong source S = s c_s^2 (tau_lb - 1/2) (Sec. 5).  The answer is Phi at the
  * fixed point of the sweep.
  *
  * Conventions for every call:
@@ -54,7 +54,7 @@ typedef enum lkp_status {
 } lkp_status;
 
 /* Velocity sets.  1D sets: Appendix A.  2D: tensor products of the 1D sets
- * (the paper's "tensorial" extension, Sec. 3) and the standard
+ * (the paper's "tensorial" extension, Sec. 4) and the standard
  * nearest-neighbour D2Q5 / D2Q9.  3D: D3Q111 (Appendix A, Table vector2). */
 typedef enum lkp_lattice {
   LKP_D1Q5 = 0,   /* N <= 3 */
@@ -66,7 +66,7 @@ typedef enum lkp_lattice {
   LKP_D2Q81 = 6,  /* N <= 5 */
   LKP_D2Q169 = 7, /* N <= 7 */
   LKP_D3Q111 = 8, /* N <= 5 */
-  LKP_D2Q37 = 9,  /* N <= 5: generated minimal 2D set (quadrature conditions of Sec. 3) */
+  LKP_D2Q37 = 9,  /* N <= 5: generated minimal 2D set (quadrature conditions of Sec. 4) */
   LKP_D2Q77 = 10, /* N <= 7: generated minimal 2D set stable at N = 7 */
   LKP_NUM_LATTICES = 11
 } lkp_lattice;
@@ -103,12 +103,12 @@ typedef struct lkp_problem_desc {
   int32_t lattice;          /* lkp_lattice */
   int64_t n[3];             /* nx, ny, nz; axes beyond dim must be 1; each >= 1;
                                nx*ny*nz < 2^29 (a population plane stays below 4 GiB) */
-  int32_t order;            /* expansion order N: 1, 3, 5 or 7 (Sec. 3) */
+  int32_t order;            /* expansion order N: 1, 3, 5 or 7 (Sec. 4) */
   int32_t precision;        /* lkp_precision */
   double tau_lb;            /* lattice relaxation time; used when knudsen <= 0 */
   double knudsen;           /* > 0: tau_lb = 1/2 + Kn * L / c_s, L = smallest box side
                                (Kn = lambda / L, Sec. 2, with lambda = c_s (tau_lb - 1/2)) */
-  const double *source;     /* s in lap(Phi) = -s (Sec. 4, Eq. poisson1: s = rho/eps),
+  const double *source;     /* s in lap(Phi) = -s (Sec. 5, Eq. poisson1: s = rho/eps),
                                nx*ny*nz FP64 values; copied at creation, the caller
                                keeps ownership */
   int32_t source_on_device; /* 1: `source` is a device pointer */
@@ -118,7 +118,7 @@ typedef struct lkp_problem_desc {
   void *stream;             /* hipStream_t for all of this handle's work; NULL = default */
   double drift[3];          /* uniform drift u (lattice units per sweep) of the
                                advection-diffusion variant, the extension named at the
-                               end of the paper (Sec. 5); all zero = the paper's diffusion
+                               end of the paper (Sec. 6); all zero = the paper's diffusion
                                scheme.  The equilibrium becomes that of a Gaussian moved by
                                u, to second order in u:
                                  phi_i += w_i [ (v_i.u)/c_s^2 + ((v_i.u)^2 - c_s^2 |u|^2)/(2 c_s^4) ]
@@ -178,7 +178,7 @@ typedef struct lkp_solve_report {
   double glups;          /* 1e-9 * cells * sweeps / wall_s */
 } lkp_solve_report;
 
-/* Sweep until the stopping rule of `o` holds (Sec. 4: the steady state of the
+/* Sweep until the stopping rule of `o` holds (Sec. 5: the steady state of the
  * iteration is the Poisson solution).  The convergence norms are FP64
  * wavefront reductions on the GPU, read back once per check.  The state stays
  * resident, so a later call resumes.  Returns LKP_ERR_NOT_CONVERGED at
@@ -231,14 +231,14 @@ typedef struct lkp_handle_info {
 
 lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info);
 
-/* The handle's equilibrium and source shapes phi_i, chi_i (Sec. 3, Eqs.
+/* The handle's equilibrium and source shapes phi_i, chi_i (Sec. 4, Eqs.
  * omega:eq, chi:eq, omega:eq3, chi:eq3, with the drift terms of a drifted
  * handle) in the order of lkp_lattice_info's velocities: Q FP64 values each
  * into host arrays (either may be NULL).  Errors: LKP_ERR_ARG. */
 lkp_status lkp_get_coefficients(lkp_handle *h, double *phi, double *chi);
 
 /* Time-dependent use (the sweep as a time step of the diffusion or
- * advection-diffusion equation, Sec. 2 and 5): set the post-collision state
+ * advection-diffusion equation, Sec. 2 and 6): set the post-collision state
  * to the equilibrium f*_i = phi_i Phi_0 of the field Phi_0 (n FP64 values,
  * host or device, caller-owned), computed on the device in the handle's
  * layout and precision; then advance with lkp_step and read lkp_get_phi.

@@ -14,7 +14,7 @@ path:
   from the orthogonality condition (Eq. quadrature / Eq. quad3, Appendix), and
   the Hermite-designed equilibrium and source shapes phi_i, chi_i
   (Eqs. omega:eq, chi:eq, omega:eq3, chi:eq3).
-* ``exact``    -- the discrete moment identities of Sec. 3 checked in exact
+* ``exact``    -- the discrete moment identities of Sec. 4 checked in exact
   (rational / algebraic) arithmetic.
 * ``sweep``    -- the discrete BGK iteration (stream, moment, collide + source)
   in plain C (``sweep.c``) and as a numpy ``roll`` reference.
@@ -24,7 +24,7 @@ path:
 * ``bf16dev``  -- the same sweep with the post-collision state stored as an
   FP32 moment and BF16 deviations (storage-precision ablation).
 * ``generator`` -- the search for new velocity sets from the quadrature
-  conditions (Sec. 3), with positive weights and a von Neumann stability
+  conditions (Sec. 4), with positive weights and a von Neumann stability
   filter.
 * ``drift``    -- the advection-diffusion variant (the equilibrium of a
   Gaussian moved by a uniform drift) and its exact complex fixed point.

@@ -2,7 +2,7 @@
 
 An ablation of the storage precision, not of the scheme: the sweep is the
 discrete BGK iteration of ``oracle.sweep`` (stream, moment, collide + source,
-Sec. 3 and 4), but between sweeps the post-collision populations are kept as
+Sec. 4 and 5), but between sweeps the post-collision populations are kept as
 
     f*_i(x) = phi_i Phi(x) + n_i(x)
 

@@ -1,7 +1,7 @@
 """Advection-diffusion variant of the scheme (test infrastructure only).
 
 The paper names time-dependent diffusion and advection-diffusion as the next
-extensions of the method (Sec. 5) and fixes no scheme for them.  Reading used
+extensions of the method (Sec. 6) and fixes no scheme for them.  Reading used
 here: the sweep is unchanged, and the equilibrium shape phi_i Phi becomes that
 of a Gaussian moved by a uniform drift u.  The ratio of the moved to the
 unmoved Gaussian at velocity v is exp(v.u / c^2 - |u|^2 / (2 c^2)); kept to

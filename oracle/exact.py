@@ -12,7 +12,7 @@ arithmetic: no rounding anywhere.
 D1Q13 is the exception: the Appendix prints c_s itself, so t is the square of
 that decimal, a rational number, and everything is plain Fraction arithmetic.
 
-Checked identities (Sec. 3, after Eqs. omega:eq and chi:eq, and Eq. CON),
+Checked identities (Sec. 4, after Eqs. omega:eq and chi:eq, and Eq. CON),
 for every monomial v^a of total degree n <= N:
     sum_i phi_i v_i^a = 1 (n=0), 0 (n=1), c_s^2 delta_ab (n=2), 0 (2<n<=N)
     sum_i chi_i v_i^a = 1 (n=0), 0 (0<n<=N)
@@ -187,7 +187,7 @@ def _shape(r2, d, order):
 
 
 def moment_identity_failures(name: str, order: int):
-    """List of (which, exponent) for which an identity of Sec. 3 fails."""
+    """List of (which, exponent) for which an identity of Sec. 4 fails."""
     lat = ExactLattice(name)
     d = lat.dim
     phis, chis = [], []

@@ -1,6 +1,6 @@
 """Velocity-set generator from the quadrature conditions (test infrastructure only).
 
-Sec. 3 reads the scheme's requirements as orthogonality conditions on the
+Sec. 4 reads the scheme's requirements as orthogonality conditions on the
 discrete velocities (Eq. quadrature in 1D, Eq. quad3 in 3D): weighted sums over
 the set must reproduce the Gaussian moments of w(v) up to the degree the
 expansion order needs, and it notes that the same procedure is a systematic way
@@ -166,7 +166,7 @@ def solve_subset(reps, cls, t_grid=None, M=None, rhs=None):
 
 def spectral_radius(found: Found, order: int, tau_lb: float, nk: int = 8) -> float:
     """Largest modulus of the one-sweep amplification over an nk^d grid of
-    wavevectors (Fourier analysis of the scheme's sweep, Sec. 3 and 4): for
+    wavevectors (Fourier analysis of the scheme's sweep, Sec. 4 and 5): for
     mode k the post-collision populations map by (1 - omega) E + omega phi 1^T E,
     E = diag(exp(-i k . v_j)), with the Hermite shape phi_i of the order."""
     from . import lattice as L

@@ -1,7 +1,7 @@
 """Oracle lattice constants (test infrastructure only).
 
 Velocity sets, weights w_i and sound speed c_s^2 are obtained by solving the
-quadrature (orthogonality) condition of Sec. 3, Eq. (quadrature) in 1D and
+quadrature (orthogonality) condition of Sec. 4, Eq. (quadrature) in 1D and
 Eq. (quad3) in 3D, in 50-digit arithmetic (mpmath).  For Hermite quadrature
 this condition is equivalent to matching the Gaussian moments
     sum_i w_i v_i^(2k) = (2k-1)!! c_s^(2k)
@@ -16,12 +16,12 @@ Sets (Appendix):
   D3Q111 (Table vector2)     N <= 5   ten shells, c_s^2 fixed by one extra
         moment class.
 The paper states the 2D extension is done with tensor Hermite polynomials
-(Sec. 3) without giving a set; D2Q25/D2Q81/D2Q169 are the tensor products of
+(Sec. 4) without giving a set; D2Q25/D2Q81/D2Q169 are the tensor products of
 D1Q5/D1Q9/D1Q13.  D2Q5 and D2Q9 are the standard nearest-neighbour sets
 (w = 1/3, 1/6 and 4/9, 1/9, 1/36 with c_s^2 = 1/3) used for the standard
 lattice Boltzmann baseline.
 
-phi_i and chi_i (Sec. 3, Eqs. omega:eq, chi:eq, omega:eq3, chi:eq3) are
+phi_i and chi_i (Sec. 4, Eqs. omega:eq, chi:eq, omega:eq3, chi:eq3) are
 written in the radial Hermite polynomials of x = v/c_s, r^2 = |x|^2 in d
 dimensions:
   R2 = r^2 - d
@@ -34,7 +34,7 @@ dimensions:
 In 1D R4 = He4 and R6 = He6 (Eqs. omega:eq, chi:eq, reading the printed
 "3 c_s^2" in the He4 numerator as 3 c_s^4, which the stated moment identities
 require); in 3D with N=5 this is Eqs. omega:eq3 and chi:eq3 exactly.  They are
-pinned by the moment identities of Sec. 3 (tests, ``oracle.exact``).
+pinned by the moment identities of Sec. 4 (tests, ``oracle.exact``).
 """
 from __future__ import annotations
 
@@ -79,7 +79,7 @@ D3Q111_SHELLS = [
 
 
 #: Velocity sets produced by the quadrature-condition search of
-#: ``oracle.generator`` (Sec. 3's systematic construction): the smallest sets
+#: ``oracle.generator`` (Sec. 4's systematic construction): the smallest sets
 #: whose shell weights are positive and which reproduce every Gaussian moment
 #: of degree <= 9 (N = 5) or <= 13 (N = 7).
 #:   D2Q37   N <= 5, components <= 3: the most compact of four 37-velocity sets;
@@ -370,7 +370,7 @@ def coefficients(lat: Lattice, order: int):
 def scaled_source(s: np.ndarray, lat: Lattice, tau_lb: float) -> np.ndarray:
     """Source S of the kinetic scheme for the Poisson right-hand side s.
 
-    Sec. 4: from S + c_s^2 tau lap(Phi) = 0 and lap(Phi) = -rho/eps, the
+    Sec. 5: from S + c_s^2 tau lap(Phi) = 0 and lap(Phi) = -rho/eps, the
     source is S = (rho/eps) c_s^2 tau with the lattice correction
     tau = tau_lb - 1/2.  Here s = rho/eps.
     """

@@ -8,7 +8,7 @@
  *   collide+source:  fout_i(x) = (1-omega) f_i(x) + omega phi_i Phi(x) + chi_i S(x)
  * which is the BGK relaxation of Eq. (boltzmann) towards the separable
  * equilibrium f_eq = phi(v) Phi (Eq. equilibrium2) with the separable source
- * chi(v) S (Sec. 3), time step 1, omega = 1/tau_lb (Sec. 4).
+ * chi(v) S (Sec. 4), time step 1, omega = 1/tau_lb (Sec. 5).
  * fin/fout hold post-collision populations as Q planes of n cells each.
  * Phi_out (may be NULL) receives the post-stream moment of this sweep.
  * Built with -ffp-contract=off so every product and sum rounds on its own.

@@ -2,13 +2,13 @@
 
 The paper never prints the discrete update; it is read here as the standard
 lattice discretisation of Eq. (boltzmann) with time step 1 and the separable
-equilibrium and source of Sec. 3:
+equilibrium and source of Sec. 4:
 
     stream:   f_i(x)   = f*_i(x - v_i)                    (periodic)
     moment:   Phi(x)   = sum_i f_i(x)
     collide:  f*_i'(x) = (1 - omega) f_i(x) + omega phi_i Phi(x) + chi_i S(x)
 
-with omega = 1/tau_lb and S = s c_s^2 (tau_lb - 1/2) (Sec. 4).  The answer of
+with omega = 1/tau_lb and S = s c_s^2 (tau_lb - 1/2) (Sec. 5).  The answer of
 the method is Phi at steady state.  Two implementations of the same sweep:
 ``sweep_c`` (plain C, OpenMP over cells, ``sweep.c``) and ``sweep_roll``
 (numpy ``roll``, for cross-checking the C one on small grids).

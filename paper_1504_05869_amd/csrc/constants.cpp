@@ -1,7 +1,7 @@
 // Host-side constants of each velocity set: quadrature weights, sound speed
 // and the Hermite-designed equilibrium/source shapes phi_i, chi_i.
 //
-// Weights come from the quadrature condition (Sec. 3, Eq. quadrature in 1D,
+// Weights come from the quadrature condition (Sec. 4, Eq. quadrature in 1D,
 // Eq. quad3 in 3D), which for Hermite quadrature amounts to reproducing the
 // Gaussian moments  sum_i w_i v^a = prod_k (a_k - 1)!! c_s^{a_k}  (even a_k).
 // All solves run in long double with partial pivoting; results are rounded
@@ -16,13 +16,13 @@
 //          again under the label c_s^2)
 //   D3Q111 the value at which all eleven cubic moment classes of degree <= 8
 //          hold with ten shell weights (Table vector2 does not print it)
-//   D2Q37, D2Q77  generated shell sets (Sec. 3's systematic construction):
+//   D2Q37, D2Q77  generated shell sets (Sec. 4's systematic construction):
 //          the value at which all 9 (degree <= 8) resp. 16 (degree <= 12)
 //          square-symmetric moment classes hold with 8 resp. 15 shell weights
 //   D2Q5, D2Q9  1/3 (standard nearest-neighbour sets)
 //
 // phi_i / w_i and chi_i / w_i in the radial Hermite polynomials of
-// r^2 = |v|^2 / c_s^2 in d dimensions (Sec. 3, Eqs. omega:eq, chi:eq,
+// r^2 = |v|^2 / c_s^2 in d dimensions (Sec. 4, Eqs. omega:eq, chi:eq,
 // omega:eq3, chi:eq3; in 1D R4 = He4 and R6 = He6):
 //   R2 = r^2 - d
 //   R4 = r^4 - 2(d+2) r^2 + d(d+2)
@@ -341,7 +341,7 @@ bool shape_coefficients(const LatticeConstants& c, int order, std::vector<long d
 
 double stability_threshold(int id, int order) {
   // Smallest tau_lb accepted.  Orders 1 and 3 need tau_lb > 1/2 (positive
-  // diffusivity c_s^2 (tau_lb - 1/2), Sec. 4).  The N = 5 and N = 7
+  // diffusivity c_s^2 (tau_lb - 1/2), Sec. 5).  The N = 5 and N = 7
   // equilibria carry negative phi_i and lose linear stability below about
   // tau_lb = 0.62 and 0.76; the limits below keep a margin above those.
   if (order <= 3) return 0.5;

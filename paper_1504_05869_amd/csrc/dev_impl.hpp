@@ -1,6 +1,6 @@
 // Lattice-kinetic sweep with BF16 deviation storage, for gfx950.
 //
-// The scheme is the fused sweep of Sec. 3 and 4 (pull streaming, moment,
+// The scheme is the fused sweep of Sec. 4 and 5 (pull streaming, moment,
 // relaxation toward phi_i Phi plus the source term); only the storage of the
 // post-collision state differs.  Per cell x:
 //   f_i(x)   = phi_i Phi(x - v_i) + n_i(x - v_i)        rebuild the streamed f

@@ -4,11 +4,11 @@
 //   1D sets (Appendix A): D1Q5 {0,+-1,+-3} (N <= 3), D1Q9 {0,+-1,+-2,+-3,+-5}
 //     (N <= 5), D1Q13 {0,+-1,...,+-6} (N <= 7).
 //   2D: the paper only says the extension uses tensor Hermite polynomials
-//     (Sec. 3); D2Q25, D2Q81, D2Q169 are tensor products of the 1D sets.
+//     (Sec. 4); D2Q25, D2Q81, D2Q169 are tensor products of the 1D sets.
 //     D2Q5 and D2Q9 are the standard nearest-neighbour sets.
 //   3D: D3Q111 (Appendix A, Table vector2), ten shells of signed
 //     permutations, N <= 5.
-//   Generated 2D sets (Sec. 3's construction from the quadrature conditions:
+//   Generated 2D sets (Sec. 4's construction from the quadrature conditions:
 //     the smallest shell sets with positive weights reproducing every Gaussian
 //     moment to the needed degree, stable at their order):
 //     D2Q37 = shells (0,0) (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,1), N <= 5;

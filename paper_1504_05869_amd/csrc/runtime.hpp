@@ -29,7 +29,7 @@ double now_s();
                              "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
   } while (0)
 
-// Convergence bookkeeping of one problem across checks (Sec. 4: the answer is
+// Convergence bookkeeping of one problem across checks (Sec. 5: the answer is
 // the steady state; the host estimates the distance to it from the one-sweep
 // change and the measured contraction per sweep).
 struct Tracker {

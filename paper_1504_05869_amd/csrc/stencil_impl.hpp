@@ -1,7 +1,7 @@
 // The sweep at omega = 1 (tau_lb = 1) as a scalar stencil, for gfx950.
 //
 // With omega = 1 the collision forgets f_i: after any sweep the post-collision
-// state is f*_i = phi_i Phi + chi_i S (Sec. 3 separable equilibrium and
+// state is f*_i = phi_i Phi + chi_i S (Sec. 4 separable equilibrium and
 // source), so the next sweep's moment is
 //     Phi'(x) = sum_i phi_i Phi(x - v_i) + G(x),   G(x) = sum_i chi_i S(x - v_i)
 // exactly.  The state shrinks from Q populations to one field, and one sweep

@@ -1,6 +1,6 @@
 // Fused lattice-kinetic Poisson sweep for gfx950 (MI355X).
 //
-// One sweep (Sec. 3 and 4 of the paper): for every cell x
+// One sweep (Sec. 4 and 5 of the paper): for every cell x
 //   f_i(x)    = f*_i(x - v_i)                                   pull streaming
 //   Phi(x)    = sum_i f_i(x)                                    moment, FP64 sum
 //   f*_i'(x)  = (1 - omega) f_i(x) + omega phi_i Phi(x) + chi_i S(x)

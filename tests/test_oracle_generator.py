@@ -1,4 +1,4 @@
-"""Pins of the velocity-set generator (quadrature conditions of Sec. 3)."""
+"""Pins of the velocity-set generator (quadrature conditions of Sec. 4)."""
 import mpmath as mp
 import numpy as np
 import pytest

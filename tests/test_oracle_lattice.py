@@ -79,7 +79,7 @@ def test_sound_speeds_match_appendix():
         assert abs(c9 - mp.mpf(GOLD["appendix_D1Q9"]["printed_cs2_label_value"])) < 1e-15
         c13 = mp.sqrt(L.get("D1Q13").c2_mp)
         assert abs(c13 - mp.mpf(GOLD["appendix_D1Q13"]["printed_cs2_label_value"])) < 1e-30
-    # Sec. 3 quotes "about 0.4" for N=3 (c_s^2 = 0.37) and "nearly 1.2" for
+    # Sec. 4 quotes "about 0.4" for N=3 (c_s^2 = 0.37) and "nearly 1.2" for
     # N=7 (c_s = 1.15): the text mixes c_s^2 and c_s as the Appendix does
     assert 0.35 < L.get("D1Q5").c2 < 0.4
     assert 1.1 < float(mp.sqrt(L.get("D1Q13").c2_mp)) < 1.2
@@ -136,7 +136,7 @@ CASES = [("D1Q5", 1), ("D1Q5", 3), ("D1Q9", 1), ("D1Q9", 3), ("D1Q9", 5), ("D1Q1
 
 @pytest.mark.parametrize("name,order", CASES)
 def test_moment_identities_exact(name, order):
-    """Sec. 3: Pi(0)=Phi, Pi(1)=0, Pi(2)=c_s^2 Phi, Pi(n>2)=0, S(0)=S, S(n>0)=0
+    """Sec. 4: Pi(0)=Phi, Pi(1)=0, Pi(2)=c_s^2 Phi, Pi(n>2)=0, S(0)=S, S(n>0)=0
     up to order N, in exact arithmetic."""
     assert E.moment_identity_failures(name, order) == []
 

@@ -191,7 +191,7 @@ def test_n1_and_n3_errors_equal_and_opposite():
 
 
 def test_text_error_percentages():
-    """Sec. 4 text on Figs 1, 3, 4 (read off plots): factor-1.5 agreement.
+    """Sec. 5 text on Figs 1, 3, 4 (read off plots): factor-1.5 agreement.
     Figs 3 and 4 share the mode k = pi/4 and so the exact same error, while the
     text quotes different numbers for them; the looser reading covers both."""
     t = GOLD["text_errors"]
