@@ -1,18 +1,24 @@
 """Benchmark of the lattice-kinetic Poisson sweep on one MI355X.
 
-Workload (one GPU): periodic 1024 x 1024 grid, higher-order scheme at order
-N = 5 on D2Q81, Kn = 0.1 (tau_lb = 118.26), FP64, source = 64 Gaussians of
-width 2 cells with N(0,1) amplitudes at seeded uniform positions, mean removed.
+Headline workload (one GPU): periodic 512^3 grid, higher-order scheme at order
+N = 5 on D3Q111 (Appendix A, Table vector2), Kn = 0.3 (tau_lb = 184.36),
+source = 4096 point-like Gaussians of width 1 cell with amplitudes +-U(1,10)
+at seeded uniform positions, mean removed; FP64 populations in two buffers
+(238 GB of the 288 GB of HBM).
 
 A step is one pass of the solver's hot path: one chunk of --chunk sweeps
 (fused pull-stream / moment / collide+source), the FP64 convergence
 reductions on the last two sweeps, the read-back of the norms and the host's
-stopping decision.  Inputs are resident in HBM before timing starts.
+stopping decision against rel-L2 1e-10 (a real decision: the convergence
+history carries across steps).  Inputs are resident in HBM before timing
+starts.
 
 Printed: one JSON line with GLUPS (cell updates per second; one update moves
 all Q populations of a cell), the roofline of the sweep kernel from HIP events
-on the solver's stream, the oracle's CPU throughput on a bounded sample, and
-extra measurements (other orders, FP32, 3D, time-to-solution).
+on the solver's stream over the timed region, the oracle's CPU throughput on a
+bounded sample, and extra measurements (other sets, orders and precisions,
+time-to-solution with each answer's error against the oracle's exact fixed
+point, serving).
 """
 from __future__ import annotations
 
@@ -29,6 +35,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 ORDERS = {1: "D2Q25", 3: "D2Q25", 5: "D2Q81", 7: "D2Q169"}
+# the headline problem: 512^3 D3Q111 N = 5, Kn = 0.3, 4096 point-like Gaussians
+C5 = {"shape": (512, 512, 512), "lattice": "D3Q111", "order": 5, "knudsen": 0.3,
+      "kind": "stiff3d", "seed": 5120}
 
 
 def bytes_per_cell(Q: int, precision: str) -> int:
@@ -103,8 +112,43 @@ def paper_context(eps=1e-3):
             "speedup_N1_over_N7": float(f"{t[1] / t[7]:.3g}")}
 
 
-def cpu_baseline(s, lattice, order, tau, seconds=15.0):
-    """Oracle C sweep (FP64, OpenMP) on the same grid for a bounded time."""
+def true_rel_l2(phi: np.ndarray, ref: np.ndarray) -> float:
+    """||phi - ref||_2 / ||ref||_2 (no mean removed: a mass drift counts)."""
+    return float(np.linalg.norm((phi - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def oracle_fixed_point(lattice, order, s, tau_lb=None, knudsen=None):
+    """The oracle's exact fixed point (spectral, FP64) of a problem; tau_lb
+    from Kn with the oracle's own mapping.  Reference generation, outside every
+    timed region."""
+    from oracle import lattice as OL
+    from oracle import spectral as SP
+    if tau_lb is None:
+        tau_lb = OL.tau_from_knudsen(knudsen, OL.get(lattice), min(s.shape))
+    return SP.fixed_point_large(lattice, order, tau_lb, s)
+
+
+def timed_solve(lkp, torch, s, lattice, order, precision, tol, ref=None, check_every=100,
+                **kw) -> dict:
+    """Solve to estimated rel-L2 `tol`; wall time, sweeps, the solver's own
+    estimate and, with `ref`, the true error against the oracle's fixed point."""
+    with lkp.Problem(s, lattice, order, precision=precision, **kw) as q:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rep = q.solve(tol_rel_l2=tol, check_every=check_every, max_sweeps=4_000_000,
+                      raise_on_error=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out = {"precision": precision, "tol_rel_l2": tol, "seconds": round(el, 4),
+               "sweeps": rep["sweeps"], "outer": rep["outer"], "status": rep["status"],
+               "est_rel_err": rep["est_rel_err"]}
+        if ref is not None:
+            out["true_rel_l2"] = true_rel_l2(q.phi_host(), ref)
+    return out
+
+
+def cpu_baseline(s, lattice, order, tau, seconds=15.0, note=""):
+    """Oracle C sweep (FP64, OpenMP) on a grid for a bounded time."""
     from oracle import sweep as SW
     prob = SW.Problem(lattice, order, tau, s)
     a = prob.zero_state()
@@ -118,42 +162,114 @@ def cpu_baseline(s, lattice, order, tau, seconds=15.0):
         a, b = b, a
         k += 1
     dt = time.perf_counter() - t0
+    grid = "x".join(str(n) for n in s.shape[::-1])
     return {"value": s.size * k / dt / 1e9, "unit": "GLUPS", "cores": SW.threads(),
             "kind": "oracle",
-            "sample": f"{k} full sweeps of the {s.shape[1]}x{s.shape[0]} {lattice} N={order} "
-                      f"FP64 grid in {dt:.1f} s"}
+            "sample": f"{k} full sweeps of the {grid} {lattice} N={order} tau_lb={tau:.2f} FP64 "
+                      f"grid in {dt:.1f} s{note}"}
+
+
+def headline(lkp, torch, args) -> dict:
+    """K timed steps of the 512^3 D3Q111 FP64 sweep (see the module docstring)."""
+    from paper_1504_05869_amd import workloads as W
+    shape, lattice, order, kn = C5["shape"], C5["lattice"], C5["order"], C5["knudsen"]
+    s = W.poisson_source(C5["kind"], shape, seed=C5["seed"])
+    n = s.size
+    p = lkp.Problem(s, lattice, order, knudsen=kn, precision="f64")
+    del s
+    info = p.info()
+    Q = info["Q"]
+    say(f"headline: {info['n']} {lattice} N={order} tau_lb={info['tau_lb']:.4f} FP64, "
+        f"{info['footprint_bytes'] / 1e9:.1f} GB resident, split P={info['velocity_groups']}")
+
+    def step():
+        # one chunk with its convergence check against the 1e-10 target; the
+        # contraction history carries over, so each check is a real decision
+        return p.solve(tol_rel_l2=1e-10, max_sweeps=args.chunk, check_every=args.chunk,
+                       use_graph=True, raise_on_error=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    say(f"headline: {args.warmup} warmup steps done, timing {args.steps} steps")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    sweeps, last = 0, None
+    for _ in range(args.steps):
+        last = step()
+        sweeps += last["sweeps"]
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # every launch of the timed region on the solver's stream (torch's current
+    # stream): the sweeps, their norm finishes; divided over the sweeps
+    ms_sweep = e0.elapsed_time(e1) / sweeps
+    p.close()
+    glups = n * sweeps / wall / 1e9
+    bpc = bytes_per_cell(Q, "f64")
+    achieved = n * bpc / (ms_sweep * 1e-3) / 1e9
+    return {
+        "metric": "GLUPS (lattice cell updates per second, all Q populations per update)",
+        "value": round(glups, 4),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D periodic 512^3 Poisson, D3Q111 N=5, Kn=0.3 "
+                               f"(tau_lb={info['tau_lb']:.4f}), 4096 Gaussians sigma=1, amplitudes "
+                               "+-U(1,10), zero mean; FP64 populations, two buffers",
+                   "grid": list(shape), "lattice": lattice, "order": order, "knudsen": kn,
+                   "sweeps_per_step": args.chunk, "velocity_groups": info["velocity_groups"],
+                   "footprint_gb": round(info["footprint_bytes"] / 1e9, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("k_sweep_d3q111_f64_512cubed"),
+                     "kernel": "k_sweep (D3Q111, FP64, two buffers)",
+                     "bytes_per_launch": n * bpc, "ms_per_launch": round(ms_sweep, 5)},
+        "paper_context": paper_context(),
+        "last_check": {"est_rel_err": last["est_rel_err"], "rate": last["rate"],
+                       "total_sweeps": last["total_sweeps"]},
+    }
 
 
 def stiff_512(lkp, torch, tol: float, chunk: int, minutes: float) -> dict:
-    """512^3 D3Q111 N=5, Kn = 0.3 (tau_lb = 184.4), 4096 point-like Gaussians:
-    FP32 sweeps + FP64 refinement (in place: 238 GB) against the plain FP64
-    sweep (two buffers: 238 GB), each solved to estimated rel-L2 `tol`.  The
-    solve runs as consecutive lkp_solve calls of `chunk` sweeps (a refinement
-    stopped by max_sweeps keeps its partial correction and resumes from it),
-    one progress line per call on stderr.  A solve still short of `tol` after
-    `minutes` of wall time reports its reached error and the contraction rate,
-    and a time extrapolated from that rate (labelled as such)."""
+    """The headline problem solved to estimated rel-L2 `tol`: FP32 sweeps +
+    FP64 refinement (in place: 242 GB) against the plain FP64 sweep (two
+    buffers: 242 GB).  The solve runs as consecutive lkp_solve calls of
+    `chunk` sweeps (a resumed call keeps the convergence history; a refinement
+    stopped by max_sweeps keeps its partial correction), one progress line per
+    call on stderr.  Each answer is compared with the oracle's exact fixed
+    point (spectral, FP64, computed on the host after the timed solves).  A
+    solve still short of `tol` after `minutes` of wall time reports its reached
+    error and a time extrapolated from its rate (labelled as such)."""
     from paper_1504_05869_amd import workloads as W
-    shape = (512, 512, 512)
+    shape = C5["shape"]
     t0 = time.perf_counter()
-    s = W.poisson_source("stiff3d", shape, seed=5120)
+    s = W.poisson_source(C5["kind"], shape, seed=C5["seed"])
     gen_s = time.perf_counter() - t0
     out = {"workload": "512^3 D3Q111 N=5 Kn=0.3, 4096 Gaussians sigma=1, amplitudes +-U(1,10), zero mean",
            "tol_rel_l2": tol, "source_generation_s": round(gen_s, 1), "runs": []}
+    phis = []
     for prec, in_place in (("f32_ir", True), ("f64", False)):
-        with lkp.Problem(s, "D3Q111", 5, knudsen=0.3, precision=prec, in_place=in_place) as q:
+        with lkp.Problem(s, "D3Q111", 5, knudsen=C5["knudsen"], precision=prec, in_place=in_place) as q:
             info = q.info()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            sweeps, outer, rep, hist = 0, 0, None, []
+            sweeps, outer, rep = 0, 0, None
             while True:
                 rep = q.solve(tol_rel_l2=tol, check_every=200, max_sweeps=chunk, raise_on_error=False)
                 sweeps += rep["sweeps"]
-                outer += rep["outer"]
+                outer = rep["outer"] if prec == "f64" else outer + rep["outer"]
                 el = time.perf_counter() - t1
-                hist.append((el, sweeps, rep["est_rel_err"]))
-                print(f"[c5] {prec} in_place={in_place} {sweeps} sweeps {el:.0f} s est {rep['est_rel_err']:.3e} "
-                      f"status {rep['status']}", file=sys.stderr, flush=True)
+                say(f"[c5] {prec} in_place={in_place} {sweeps} sweeps {el:.0f} s est "
+                    f"{rep['est_rel_err']:.3e} status {rep['status']}")
                 if rep["status"] == 0 or el > 60 * minutes:
                     break
             torch.cuda.synchronize()
@@ -166,16 +282,25 @@ def stiff_512(lkp, torch, tol: float, chunk: int, minutes: float) -> dict:
                 import math
                 more = math.log(tol / rep["est_rel_err"]) / math.log(rep["rate"])
                 run["extrapolated_seconds"] = round(el + more * el / max(sweeps, 1), 1)
+            phis.append(q.phi_host())
             out["runs"].append(run)
+    t2 = time.perf_counter()
+    ref = oracle_fixed_point("D3Q111", 5, s, knudsen=C5["knudsen"])
+    out["reference_generation_s"] = round(time.perf_counter() - t2, 1)
+    for run, phi in zip(out["runs"], phis):
+        run["true_rel_l2"] = true_rel_l2(phi, ref)
     return out
 
 
 def serving_run(n_requests: int, rate: float, full_sizes: bool = False) -> dict:
     """Serving stream: continuous batching (FP32 + refinement) against the same
-    trace solved one at a time in FP64, both to estimated rel-L2 1e-6.  The
-    default size mix is scaled down so that the run takes seconds; full_sizes
-    draws from {128..2048}^2 and {64,128,256}^3 with a 240 GiB HBM budget."""
+    trace solved one at a time in FP64, both to estimated rel-L2 1e-6.  Every
+    answer is read back at retirement and compared afterwards with the
+    oracle's exact fixed point.  The default size mix is scaled down so that
+    the run takes seconds; full_sizes draws from {128..2048}^2 and
+    {64,128,256}^3 with a 240 GiB HBM budget."""
     from paper_1504_05869_amd import serve
+    from paper_1504_05869_amd import workloads as W
     if full_sizes:
         s2 = tuple((n, n) for n in (128, 256, 512, 1024, 2048))
         s3 = tuple((n, n, n) for n in (64, 128, 256))
@@ -186,34 +311,184 @@ def serving_run(n_requests: int, rate: float, full_sizes: bool = False) -> dict:
         budget = 64 << 30
     reqs = serve.make_stream(n_requests, rate=rate, seed=2024, sizes2d=s2, sizes3d=s3)
 
-    def say(msg):
+    def prog(msg):
         if full_sizes:
-            print(f"[serving] {msg}", file=sys.stderr, flush=True)
+            say(f"[serving] {msg}")
 
-    srv = serve.Server(serve.GpuBackend("f32_ir"), hbm_budget=budget, sweeps_per_tick=50,
-                       tol=1e-6, progress=say)
+    srv = serve.Server(serve.GpuBackend("f32_ir", keep_phi=True), hbm_budget=budget,
+                       sweeps_per_tick=50, tol=1e-6, progress=prog)
     res, summ = srv.run(reqs)
-    base, bsum = serve.run_one_at_a_time(reqs, "f64", tol=1e-6, check_every=50, progress=say)
+    base, bsum = serve.run_one_at_a_time(reqs, "f64", tol=1e-6, check_every=50, keep_phi=True,
+                                         progress=prog)
+    # true errors against the oracle (after both legs; not timed)
+    errs = {"batched": [], "one_at_a_time": []}
+    by_rid = {r.rid: r for r in reqs}
+    for leg, results in (("batched", res), ("one_at_a_time", base)):
+        for r in results:
+            if r.phi is None:
+                continue
+            q = by_rid[r.rid]
+            s = W.poisson_source(q.kind, q.shape, seed=q.seed)
+            ref = oracle_fixed_point(q.lattice, q.order, s, knudsen=q.knudsen)
+            errs[leg].append(true_rel_l2(r.phi, ref))
+            r.phi = None
     keys = ("completed", "problems_per_s", "p50_latency_s", "p99_latency_s", "makespan_s",
             "sweeps_total")
     sizes = ("{128,256,512,1024,2048}^2 and 3D D3Q111 N=5 {64,128,256}^3" if full_sizes else
              "{64,128,256,512}^2 and 3D D3Q111 N=5 {32,48,64}^3")
+
+    def err_stats(v):
+        return {"max": max(v), "median": float(np.median(v)), "count": len(v)} if v else None
+
     return {"stream": f"{n_requests} requests, Poisson arrivals at {rate}/s, 2D D2Q81 N=5 "
                       f"{sizes}, Kn~U(0.05,0.5), Gaussian blobs, retire at estimated rel-L2 1e-6",
             "hbm_budget_bytes": budget,
             "batched_f32_ir": {k: summ[k] for k in keys}
                               | {k: summ[k] for k in ("ticks", "graph_captures", "graph_replays")
-                                 if k in summ},
-            "one_at_a_time_f64": {k: bsum[k] for k in keys},
+                                 if k in summ}
+                              | {"true_rel_l2": err_stats(errs["batched"])},
+            "one_at_a_time_f64": {k: bsum[k] for k in keys}
+                                 | {"true_rel_l2": err_stats(errs["one_at_a_time"])},
             "speedup_problems_per_s": summ["problems_per_s"] / bsum["problems_per_s"]}
+
+
+def say(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def extras_rates(lkp, torch, W) -> list:
+    """Per-sweep rates of the other sets, orders, precisions and forms."""
+    s = W.poisson_source("blobs2d", (1024, 1024), seed=12345)
+    kn = 0.1
+    extras = []
+    for N, lat in ORDERS.items():
+        for prec in ("f64", "f32"):
+            extras.append(dict(sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200),
+                               grid="1024^2"))
+    # generated minimal sets (square-symmetric shells) for the same orders
+    for N, lat in ((5, "D2Q37"), (7, "D2Q77")):
+        for prec in ("f64", "f32"):
+            extras.append(dict(sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200),
+                               form="generated set", grid="1024^2"))
+    # in place (one population buffer): every sweep pair gathers/scatters once
+    for prec in ("f64", "f32"):
+        extras.append(dict(sweep_rate(lkp, torch, s, "D2Q81", 5, prec, knudsen=kn, sweeps=200,
+                                      in_place=True), grid="1024^2"))
+    s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
+    for prec in ("f32", "f64"):
+        extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
+                                      sweeps=40, population_sweep=True), grid="256^3"))
+        extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
+                                      sweeps=40, population_sweep=True, in_place=True),
+                           grid="256^3"))
+    # BF16 deviation storage (ablation): plain deviation sweeps; bytes = n_i
+    # read + write (BF16), Phi read + write and S (FP32)
+    r = sweep_rate(lkp, torch, s, "D2Q81", 5, "bf16dev_ir", knudsen=kn, sweeps=200)
+    bpc_dev = 4 * r_q(lkp, "D2Q81") + 12
+    r.update(form="BF16 deviation storage", grid="1024^2",
+             gbs=s.size * bpc_dev / (r["ms_per_sweep"] * 1e-3) / 1e9)
+    r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
+    extras.append(r)
+    # tau_lb = 1: the stencil form (state Phi, 3 values moved per cell)
+    for prec in ("f32", "f64"):
+        r = sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0, sweeps=200)
+        b = 4 if prec == "f32" else 8
+        r.update(form="stencil (tau_lb=1)", grid="256^3",
+                 gbs=s3.size * 3 * b / (r["ms_per_sweep"] * 1e-3) / 1e9)
+        r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
+        extras.append(r)
+    return [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in e.items()} for e in extras]
+
+
+def extras_tts(lkp, torch, W) -> dict:
+    """Time to solution, each answer checked against the oracle's fixed point."""
+    out = {}
+    # 64^2 standard LB (D2Q5, N = 1, tau_lb = 1), stop at max |dPhi| < 1e-10:
+    # cache resident, reported as such
+    s1 = W.poisson_source("sine", (64, 64))
+    ref1 = oracle_fixed_point("D2Q5", 1, s1, tau_lb=1.0)
+    with lkp.Problem(s1, "D2Q5", 1, tau_lb=1.0) as q:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rep = q.solve(tol_maxchange=1e-10, check_every=1, max_sweeps=100_000)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        phi = q.phi_host()
+    out["c1_64x64_d2q5"] = {"rule": "max|dPhi| < 1e-10", "seconds": round(el, 4),
+                            "sweeps": rep["sweeps"], "true_rel_l2": true_rel_l2(phi, ref1),
+                            "phi_16_16": float(phi[16, 16]),
+                            "note": "160 KB of populations: cache resident, launch bound"}
+    # 256^3 D3Q111 N=5 at tau_lb = 1 (512 Gaussians + sine background): stencil
+    # form (F32_IR, FP64) and population sweep (F32_IR), to rel-L2 1e-6
+    s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
+    ref3 = oracle_fixed_point("D3Q111", 5, s3, tau_lb=1.0)
+    tts3 = []
+    for prec in ("f32_ir", "f64"):
+        tts3.append(dict(timed_solve(lkp, torch, s3, "D3Q111", 5, prec, 1e-6, ref=ref3, check_every=200,
+                                     tau_lb=1.0), form="stencil (tau_lb=1)"))
+    tts3.append(dict(timed_solve(lkp, torch, s3, "D3Q111", 5, "f32_ir", 1e-6, ref=ref3, check_every=200,
+                                 tau_lb=1.0, population_sweep=True), form="population sweep"))
+    out["time_to_solution_256cubed"] = tts3
+    del s3, ref3
+    # 1024^2 D2Q81 N=5 Kn=0.1: FP64, FP32 + refinement, BF16 deviation + refinement
+    s = W.poisson_source("blobs2d", (1024, 1024), seed=12345)
+    ref = oracle_fixed_point("D2Q81", 5, s, knudsen=0.1)
+    tts = []
+    for prec, tol in (("f64", 1e-10), ("f32_ir", 1e-10), ("bf16dev_ir", 1e-10),
+                      ("f64", 1e-6), ("f32_ir", 1e-6), ("bf16dev_ir", 1e-6)):
+        tts.append(timed_solve(lkp, torch, s, "D2Q81", 5, prec, tol, ref=ref, knudsen=0.1))
+    out["time_to_solution_1024x1024_d2q81"] = tts
+    # advection-diffusion variant on the same grid: drift u = (0.05, 0.02)
+    # (Peclet number |u| L / D ~ 0.6 at Kn = 0.1), rate and time to 1e-6
+    from oracle import drift as DR
+    from oracle import lattice as OL
+    u = (0.05, 0.02)
+    tau = OL.tau_from_knudsen(0.1, OL.get("D2Q81"), 1024)
+    refd = DR.fixed_point("D2Q81", 5, tau, s, u)
+    adv = []
+    for prec in ("f64", "f32"):
+        r = sweep_rate(lkp, torch, s, "D2Q81", 5, prec, knudsen=0.1, sweeps=200, drift=u)
+        r.update(form="advection-diffusion", drift=u)
+        adv.append({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()})
+    for prec in ("f64", "f32_ir"):
+        adv.append(dict(timed_solve(lkp, torch, s, "D2Q81", 5, prec, 1e-6, ref=refd, knudsen=0.1,
+                                    drift=u), drift=u))
+    out["advection_diffusion"] = adv
+    return out
+
+
+def configs_matrix(lkp, torch, W) -> dict:
+    """The 1024^2 workload at every order and Knudsen number, FP64 and FP32 +
+    refinement, to rel-L2 1e-6 with true errors; the 256^3 BF16 deviation
+    ablation (population sweep, tau_lb = 1) as a separate run."""
+    s = W.poisson_source("blobs2d", (1024, 1024), seed=12345)
+    rows = []
+    for N, lat in ORDERS.items():
+        for kn in (0.01, 0.1, 0.5):
+            ref = oracle_fixed_point(lat, N, s, knudsen=kn)
+            for prec in ("f64", "f32_ir"):
+                r = timed_solve(lkp, torch, s, lat, N, prec, 1e-6, ref=ref, knudsen=kn)
+                r.update(lattice=lat, order=N, knudsen=kn)
+                say(f"[configs] {lat} N={N} Kn={kn} {prec}: {r['seconds']} s, {r['sweeps']} sweeps, "
+                    f"true {r['true_rel_l2']:.2e}")
+                rows.append(r)
+    s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
+    ref3 = oracle_fixed_point("D3Q111", 5, s3, tau_lb=1.0)
+    abl = []
+    for prec in ("bf16dev_ir", "f32_ir"):
+        r = timed_solve(lkp, torch, s3, "D3Q111", 5, prec, 1e-6, ref=ref3, check_every=200,
+                        tau_lb=1.0, population_sweep=True)
+        say(f"[configs] 256^3 population sweep {prec}: {r['seconds']} s, true {r['true_rel_l2']:.2e}")
+        abl.append(r)
+    return {"c2_1024x1024": rows, "c3_256cubed_population_sweep": abl}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--chunk", type=int, default=100, help="sweeps per step")
+    ap.add_argument("--chunk", type=int, default=50, help="sweeps per step")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -225,10 +500,13 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-sizes", choices=("scaled", "full"), default="scaled",
                     help="serving size mix: scaled (seconds) or full (up to 2048^2 and 256^3)")
-    ap.add_argument("--c5", action="store_true",
-                    help="only the 512^3 stiff workload: FP32+IR in place vs FP64 (long)")
+    ap.add_argument("--c5-tts", action="store_true",
+                    help="only the headline problem solved to --c5-tol: FP32+IR in place vs FP64 (long)")
     ap.add_argument("--c5-tol", type=float, default=1e-10)
     ap.add_argument("--c5-minutes", type=float, default=7.0, help="wall-time cap per solve")
+    ap.add_argument("--configs", action="store_true",
+                    help="only the order x Knudsen x precision matrix of the 1024^2 workload and "
+                         "the 256^3 BF16 ablation (a few minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -242,15 +520,13 @@ def main():
     from paper_1504_05869_amd import workloads as W
 
     torch.cuda.set_device(0)
-    if args.c5:
+    if args.c5_tts:
         print(json.dumps({"stiff_512cubed": stiff_512(lkp, torch, args.c5_tol, 2000, args.c5_minutes)}),
               flush=True)
         return
-    shape = (1024, 1024)
-    lattice, order, kn, precision = "D2Q81", 5, 0.1, "f64"
-    s = W.poisson_source("blobs2d", shape, seed=12345)
-    n = s.size
-
+    if args.configs:
+        print(json.dumps({"configs": configs_matrix(lkp, torch, W)}), flush=True)
+        return
     if args.calibrate_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
@@ -259,165 +535,26 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    p = lkp.Problem(s, lattice, order, knudsen=kn, precision=precision)
-    info = p.info()
-    Q = info["Q"]
-
-    def step():
-        # one chunk with the convergence check; the unreachable tolerance keeps
-        # the solver going, so each call does exactly `chunk` sweeps
-        return p.solve(tol_rel_l2=1e-300, max_sweeps=args.chunk, check_every=args.chunk,
-                       use_graph=True, raise_on_error=False)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    last = None
-    for _ in range(args.steps):
-        last = step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sweeps = args.steps * args.chunk
-    glups = n * sweeps / wall / 1e9
-    # sweep kernel duration: events around plain sweeps on the same stream
-    p.sync()
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    k0.record()
-    p.step(args.chunk * 5)
-    k1.record()
-    k1.synchronize()
-    ms_sweep = k0.elapsed_time(k1) / (args.chunk * 5)
-    p.close()
-    bpc = bytes_per_cell(Q, precision)
-    achieved = n * bpc / (ms_sweep * 1e-3) / 1e9
-
-    out = {
-        "metric": "GLUPS (lattice cell updates per second, all Q populations per update)",
-        "value": round(glups, 4),
-        "unit": "GLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "2D periodic 1024x1024 Poisson, D2Q81 N=5, Kn=0.1 "
-                               f"(tau_lb={info['tau_lb']:.4f}), 64 Gaussians sigma=2, FP64",
-                   "grid": [1024, 1024], "lattice": lattice, "order": order, "knudsen": kn,
-                   "sweeps_per_step": args.chunk, "velocity_groups": info["velocity_groups"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("k_sweep_d2q81_f64_1024x1024"),
-                     "kernel": "k_sweep (D2Q81, FP64)",
-                     "bytes_per_launch": n * bpc, "ms_per_launch": round(ms_sweep, 5)},
-        "paper_context": paper_context(),
-        "last_check": {"est_rel_err": last["est_rel_err"], "rate": last["rate"]},
-    }
-
+    out = headline(lkp, torch, args)
+    say(f"headline: {out['value']} GLUPS, sweep {out['roofline']['achieved']} GB/s")
     if not args.no_extras and not args.serving_only:
-        extras = []
-        for N, lat in ORDERS.items():
-            for prec in ("f64", "f32"):
-                r = sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200)
-                extras.append(r)
-        # generated minimal sets (square-symmetric shells) for the same orders
-        for N, lat in ((5, "D2Q37"), (7, "D2Q77")):
-            for prec in ("f64", "f32"):
-                extras.append(dict(sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200),
-                                   form="generated set"))
-        # in place (one population buffer): every sweep pair gathers/scatters once
-        for prec in ("f64", "f32"):
-            extras.append(sweep_rate(lkp, torch, s, lattice, order, prec, knudsen=kn, sweeps=200,
-                                     in_place=True))
-        s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
-        for prec in ("f32", "f64"):
-            extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
-                                          sweeps=40, population_sweep=True), grid="256^3"))
-            extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
-                                          sweeps=40, population_sweep=True, in_place=True),
-                               grid="256^3"))
-        # BF16 deviation storage (ablation): plain deviation sweeps on the
-        # headline problem; bytes = n_i read + write (BF16), Phi read + write
-        # and S (FP32)
-        r = sweep_rate(lkp, torch, s, lattice, order, "bf16dev_ir", knudsen=kn, sweeps=200)
-        bpc_dev = 4 * r_q(lkp, lattice) + 12
-        r.update(form="BF16 deviation storage", gbs=n * bpc_dev / (r["ms_per_sweep"] * 1e-3) / 1e9)
-        r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
-        extras.append(r)
-        # tau_lb = 1: the stencil form (state Phi, 3 values moved per cell)
-        for prec in ("f32", "f64"):
-            r = sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0, sweeps=200)
-            b = 4 if prec == "f32" else 8
-            r.update(form="stencil (tau_lb=1)", grid="256^3",
-                     gbs=s3.size * 3 * b / (r["ms_per_sweep"] * 1e-3) / 1e9)
-            r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
-            extras.append(r)
-        out["sweeps"] = [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in e.items()}
-                         for e in extras]
+        out["sweeps"] = extras_rates(lkp, torch, W)
+        say("extras: rates done")
     if not args.no_extras and not args.serving_only and not args.no_tts:
-        # 256^3 D3Q111 N=5 at tau_lb = 1 (512 Gaussians + sine background):
-        # time to rel-L2 1e-6 in FP32 + refinement and in FP64, stencil form
-        s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
-        tts3 = []
-        for prec in ("f32_ir", "f64"):
-            with lkp.Problem(s3, "D3Q111", 5, tau_lb=1.0, precision=prec) as q:
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                rep = q.solve(tol_rel_l2=1e-6, check_every=200, max_sweeps=2_000_000)
-                torch.cuda.synchronize()
-                tts3.append({"precision": prec, "tol_rel_l2": 1e-6, "form": "stencil (tau_lb=1)",
-                             "seconds": round(time.perf_counter() - t1, 4), "sweeps": rep["sweeps"],
-                             "outer": rep["outer"], "est_rel_err": rep["est_rel_err"]})
-        out["time_to_solution_256cubed"] = tts3
-        del s3
-    if not args.no_extras and not args.serving_only and not args.no_tts:
-        # time-to-solution on the headline problem, FP64 and FP32 + refinement
-        tts = []
-        for prec, tol in (("f64", 1e-10), ("f32_ir", 1e-10), ("bf16dev_ir", 1e-10),
-                          ("f64", 1e-6), ("f32_ir", 1e-6), ("bf16dev_ir", 1e-6)):
-            with lkp.Problem(s, lattice, order, knudsen=kn, precision=prec) as q:
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                rep = q.solve(tol_rel_l2=tol, check_every=100, max_sweeps=2_000_000)
-                torch.cuda.synchronize()
-                tts.append({"precision": prec, "tol_rel_l2": tol,
-                            "seconds": round(time.perf_counter() - t1, 4),
-                            "sweeps": rep["sweeps"], "outer": rep["outer"],
-                            "est_rel_err": rep["est_rel_err"]})
-        out["time_to_solution"] = tts
-        # advection-diffusion variant on the headline grid: drift u = (0.05, 0.02)
-        # (Peclet number |u| L / D ~ 0.6 at Kn = 0.1), rate and time to 1e-6
-        u = (0.05, 0.02)
-        adv = []
-        for prec in ("f64", "f32"):
-            r = sweep_rate(lkp, torch, s, lattice, order, prec, knudsen=kn, sweeps=200, drift=u)
-            r.update(form="advection-diffusion", drift=u)
-            adv.append({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()})
-        for prec in ("f64", "f32_ir"):
-            with lkp.Problem(s, lattice, order, knudsen=kn, precision=prec, drift=u) as q:
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                rep = q.solve(tol_rel_l2=1e-6, check_every=100, max_sweeps=2_000_000)
-                torch.cuda.synchronize()
-                adv.append({"precision": prec, "tol_rel_l2": 1e-6, "drift": u,
-                            "seconds": round(time.perf_counter() - t1, 4),
-                            "sweeps": rep["sweeps"], "outer": rep["outer"],
-                            "est_rel_err": rep["est_rel_err"]})
-        out["advection_diffusion"] = adv
-
+        out.update(extras_tts(lkp, torch, W))
+        say("extras: time to solution done")
     if (not args.no_extras or args.serving_only) and not args.no_serving:
         out["serving"] = serving_run(args.serve_requests, args.serve_rate,
                                      full_sizes=args.serve_sizes == "full")
-
+        say("extras: serving done")
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(s, lattice, order, info["tau_lb"], args.cpu_seconds)
+        # the oracle on the host cores, at the headline's set, order and
+        # tau_lb, on 256^3 (512^3 in FP64 needs 238 GB of host memory)
+        from oracle import lattice as OL
+        tau = OL.tau_from_knudsen(C5["knudsen"], OL.get(C5["lattice"]), C5["shape"][0])
+        s_cpu = W.poisson_source(C5["kind"], (256, 256, 256), seed=C5["seed"])
+        out["cpu_baseline"] = cpu_baseline(s_cpu, C5["lattice"], C5["order"], tau, args.cpu_seconds,
+                                           note=" (per-cell rate applies to the 512^3 workload)")
     print(json.dumps(out), flush=True)
 
 

@@ -181,8 +181,12 @@ typedef struct lkp_solve_report {
 /* Sweep until the stopping rule of `o` holds (Sec. 5: the steady state of the
  * iteration is the Poisson solution).  The convergence norms are FP64
  * wavefront reductions on the GPU, read back once per check.  The state stays
- * resident, so a later call resumes.  Returns LKP_ERR_NOT_CONVERGED at
- * max_sweeps, LKP_ERR_DIVERGED on non-finite values or growth.  `rep` may be
+ * resident, so a later call resumes; for F64 and F32 handles the convergence
+ * history (last check's change, measured contraction) carries over too, so the
+ * first check of a resumed call already yields an error estimate (it restarts
+ * after lkp_set_populations / lkp_set_equilibrium).  Refinement handles resume
+ * from the residual of the current FP64 state.  Returns LKP_ERR_NOT_CONVERGED
+ * at max_sweeps, LKP_ERR_DIVERGED on non-finite values or growth.  `rep` may be
  * NULL. */
 lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *rep);
 
@@ -240,11 +244,12 @@ lkp_status lkp_get_coefficients(lkp_handle *h, double *phi, double *chi);
 /* Time-dependent use (the sweep as a time step of the diffusion or
  * advection-diffusion equation, Sec. 2 and 6): set the post-collision state
  * to the equilibrium f*_i = phi_i Phi_0 of the field Phi_0 (n FP64 values,
- * host or device, caller-owned), computed on the device in the handle's
- * layout and precision; then advance with lkp_step and read lkp_get_phi.
- * Allocates Q*n*8 + n*8 bytes of temporary device memory for the call.
+ * host or device, caller-owned), computed on the device straight into the
+ * handle's state, in its layout and precision (a host field is staged through
+ * the handle's own Phi buffer): no device memory is allocated, so it works at
+ * any size the handle holds.  Then advance with lkp_step and read lkp_get_phi.
  * Errors: LKP_ERR_ARG, LKP_ERR_UNSUPPORTED (tau_lb = 1 stencil form),
- * LKP_ERR_OOM, LKP_ERR_HIP. */
+ * LKP_ERR_HIP. */
 lkp_status lkp_set_equilibrium(lkp_handle *h, const double *phi0, int32_t phi0_is_device);
 
 /* Wait for all of the handle's queued work. */

@@ -75,59 +75,10 @@ def sweep(p: SW.Problem, n: np.ndarray, Phi: np.ndarray, S: np.ndarray | None = 
     return n_new, Phi_s
 
 
-def sweep_fp32(p: SW.Problem, n: np.ndarray, Phi: np.ndarray, S32: np.ndarray, groups: int = 1):
-    """The same sweep evaluated in FP32 arithmetic, one rounding per operation,
-    in the order a GPU kernel with FP32 compute takes them:
-        t = phi_i Phi(x - v_i);  f_i = t + n_i(x - v_i)
-        Phi' = sum of f_i in FP64 (velocities split into `groups` consecutive
-               runs of ceil(Q / groups), each summed in order, then the run
-               sums added in order), stored as fp32(Phi')
-        n'_i = bf16(((1 - omega) (f_i - phi_i Phi')) + chi_i S)
-    with phi_i, chi_i, 1 - omega and S rounded to FP32 first.  BF16 rounding
-    is a quantisation decision; taking it on FP32 values as the kernel does
-    makes the stored deviations comparable value by value."""
-    f32 = np.float32
-    phi = p.phi.astype(f32)
-    chi = p.chi.astype(f32)
-    om1 = f32(1.0 - p.omega)
-    S32 = np.asarray(S32).astype(f32)
-    Phi32 = np.asarray(Phi).astype(f32)
-    n32 = np.asarray(n).astype(f32)
-    Q = p.lat.Q
-    axes = tuple(range(-1, -p.lat.dim - 1, -1))
-    f = np.empty((Q,) + p.shape, dtype=f32)
-    for i, v in enumerate(p.lat.v):
-        shift = tuple(int(c) for c in v)
-        t = phi[i] * np.roll(Phi32, shift=shift, axis=axes)
-        f[i] = t + np.roll(n32[i], shift=shift, axis=axes)
-    qg = -(-Q // groups)
-    total = None
-    for g in range(groups):
-        part = np.zeros(p.shape)
-        for i in range(g * qg, min(Q, (g + 1) * qg)):
-            part = part + f[i].astype(np.float64)
-        total = part if total is None else total + part
-    Ph = total.astype(f32)
-    n_new = np.empty((Q,) + p.shape)
-    for i in range(Q):
-        a = phi[i] * Ph
-        b = f[i] - a
-        c = om1 * b
-        d = c + chi[i] * S32
-        n_new[i] = round_bf16(d.astype(np.float64))
-    return n_new, Ph.astype(np.float64)
-
-
-def run(p: SW.Problem, sweeps: int, S: np.ndarray | None = None, rounding: bool = True,
-        fp32_groups: int = 0):
-    """`sweeps` sweeps from rest (n = 0, Phi = 0); returns (Phi, n).
-    fp32_groups > 0 evaluates each sweep with ``sweep_fp32`` (S is then the
-    FP32 source) and that many velocity groups in the moment sum."""
+def run(p: SW.Problem, sweeps: int, S: np.ndarray | None = None, rounding: bool = True):
+    """`sweeps` sweeps from rest (n = 0, Phi = 0); returns (Phi, n)."""
     n = np.zeros((p.lat.Q,) + p.shape)
     Phi = np.zeros(p.shape)
     for _ in range(sweeps):
-        if fp32_groups > 0:
-            n, Phi = sweep_fp32(p, n, Phi, S if S is not None else p.S, fp32_groups)
-        else:
-            n, Phi = sweep(p, n, Phi, S, rounding)
+        n, Phi = sweep(p, n, Phi, S, rounding)
     return Phi, n

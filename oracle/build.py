@@ -1,18 +1,19 @@
-"""Compile the oracle's C sweep (test infrastructure only)."""
+"""Compile the oracle's C sources (test infrastructure only)."""
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "sweep.c")
+SRCS = [os.path.join(HERE, "sweep.c"), os.path.join(HERE, "spectral.c")]
 LIB = os.path.join(HERE, "_oracle_sweep.so")
 
 
 def build(force: bool = True) -> str:
     """Build oracle/_oracle_sweep.so with gcc (-O2, OpenMP, no FP contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    stale = not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(s) for s in SRCS)
+    if force or stale:
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off",
-                               "-fPIC", "-shared", "-std=c11", SRC, "-o", tmp])
+                               "-fPIC", "-shared", "-std=c11", *SRCS, "-lm", "-o", tmp])
         os.replace(tmp, LIB)
     return LIB
 

@@ -164,11 +164,27 @@ def solve_subset(reps, cls, t_grid=None, M=None, rhs=None):
     return found
 
 
-def spectral_radius(found: Found, order: int, tau_lb: float, nk: int = 8) -> float:
+def max_amplification(v: np.ndarray, phi: np.ndarray, tau_lb: float, nk: int) -> float:
     """Largest modulus of the one-sweep amplification over an nk^d grid of
     wavevectors (Fourier analysis of the scheme's sweep, Sec. 4 and 5): for
     mode k the post-collision populations map by (1 - omega) E + omega phi 1^T E,
-    E = diag(exp(-i k . v_j)), with the Hermite shape phi_i of the order."""
+    E = diag(exp(-i k . v_j)).  v: (Q, d) integer velocities, phi: (Q,)."""
+    V = np.asarray(v, dtype=np.float64)
+    om = 1.0 / tau_lb
+    worst = 0.0
+    ks = np.linspace(0.0, 2.0 * np.pi, nk, endpoint=False)
+    # many small eigenproblems: BLAS threads only contend here
+    with threadpool_limits(1):
+        for k in itertools.product(ks, repeat=V.shape[1]):
+            e = np.exp(-1j * (V @ np.array(k)))
+            M = (1.0 - om) * np.diag(e) + om * np.outer(phi, e)
+            worst = max(worst, float(np.max(np.abs(np.linalg.eigvals(M)))))
+    return worst
+
+
+def spectral_radius(found: Found, order: int, tau_lb: float, nk: int = 8) -> float:
+    """``max_amplification`` of the order-N scheme on a generated set, with
+    the Hermite shape phi_i of the order."""
     from . import lattice as L
     v, w = found.velocities()
     with mp.workdps(30):
@@ -178,18 +194,16 @@ def spectral_radius(found: Found, order: int, tau_lb: float, nk: int = 8) -> flo
             r2 = mp.mpf(int(sum(int(c) * int(c) for c in vec))) / t
             p, _ = L.shape_factors(r2, found.dim, order)
             phi.append(float(wi * p))
-    phi = np.array(phi)
-    V = v.astype(np.float64)
-    om = 1.0 / tau_lb
-    worst = 0.0
-    ks = np.linspace(0.0, 2.0 * np.pi, nk, endpoint=False)
-    # many small eigenproblems: BLAS threads only contend here
-    with threadpool_limits(1):
-        for k in itertools.product(ks, repeat=found.dim):
-            e = np.exp(-1j * (V @ np.array(k)))
-            M = (1.0 - om) * np.diag(e) + om * np.outer(phi, e)
-            worst = max(worst, float(np.max(np.abs(np.linalg.eigvals(M)))))
-    return worst
+    return max_amplification(v, np.array(phi), tau_lb, nk)
+
+
+def lattice_spectral_radius(lattice: str, order: int, tau_lb: float, nk: int = 8) -> float:
+    """``max_amplification`` of the order-N scheme on a named set of
+    ``oracle.lattice``."""
+    from . import lattice as L
+    lat = L.get(lattice)
+    phi, _ = L.coefficients(lat, order)
+    return max_amplification(lat.v3()[:, :lat.dim], phi, tau_lb, nk)
 
 
 def stable(found: Found, order: int, taus=(1.0, 100.0), nk: int = 8, tol: float = 1e-9) -> bool:

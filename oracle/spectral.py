@@ -73,6 +73,39 @@ def fixed_point(lattice: str, order: int, tau_lb: float, s: np.ndarray):
     return np.real(np.fft.ifftn(np.fft.fftn(S) * R))
 
 
+def transfer_c(shape, lattice: str, order: int, tau_lb: float, half: bool = False):
+    """The same A(k)/D(k) from the plain C loop of ``spectral.c`` (OpenMP, one
+    sine/cosine table over the grid's common phase denominator), for grids
+    where the per-velocity numpy passes are slow.  half=True returns only the
+    modes of a real FFT (last axis nx//2 + 1), which suffice since R is even."""
+    from .sweep import _lib, grid3
+    lat = L.get(lattice)
+    phi, chi = L.coefficients(lat, order)
+    nx, ny, nz = grid3(shape)
+    nkx = nx // 2 + 1 if half else nx
+    R = np.empty(tuple(shape)[:-1] + (nkx,))
+    v3 = np.ascontiguousarray(lat.v3())
+    rc = _lib().oracle_transfer(nx, ny, nz, nkx, lat.Q, v3.ctypes.data, 1.0 / float(tau_lb),
+                                np.ascontiguousarray(phi).ctypes.data,
+                                np.ascontiguousarray(chi).ctypes.data, R.ctypes.data)
+    if rc:
+        raise RuntimeError(f"oracle_transfer rejected its arguments ({rc})")
+    return R
+
+
+def fixed_point_large(lattice: str, order: int, tau_lb: float, s: np.ndarray, workers: int = -1):
+    """``fixed_point`` for large grids: real FFTs (scipy, ``workers`` threads)
+    and the half-spectrum transfer of ``transfer_c``.  Same formula."""
+    import scipy.fft as F
+    s = np.asarray(s, dtype=np.float64)
+    lat = L.get(lattice)
+    S = L.scaled_source(s, lat, tau_lb)
+    Sh = F.rfftn(S, workers=workers)
+    del S
+    Sh *= transfer_c(s.shape, lattice, order, tau_lb, half=True)
+    return F.irfftn(Sh, s=s.shape, workers=workers)
+
+
 def continuum_poisson(s: np.ndarray):
     """Spectral solution of the continuum periodic Poisson problem lap(Phi) = -s."""
     s = np.asarray(s, dtype=np.float64)

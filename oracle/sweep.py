@@ -29,8 +29,7 @@ def _lib():
     global _LIB
     if _LIB is None:
         from .build import LIB, build
-        if not os.path.exists(LIB):
-            build()
+        build(force=False)      # compiles only when missing or older than its sources
         lib = ctypes.CDLL(LIB)
         lib.oracle_sweep.restype = ctypes.c_int
         lib.oracle_sweep.argtypes = [
@@ -38,6 +37,10 @@ def _lib():
             ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_transfer.restype = ctypes.c_int
+        lib.oracle_transfer.argtypes = [
+            ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _LIB = lib
     return _LIB
 

@@ -423,6 +423,8 @@ lkp_status lkp_group_add(lkp_group *g, lkp_handle *h, const lkp_solve_opts *o) {
   h->g_sweeps = 0;
   h->trk = Tracker();
   ir_reset(h);
+  h->solo_split = h->split;
+  h->solo_tuned = h->tuned;
   h->split = g->P;
   h->tuned = true;
   g->members.push_back(h);
@@ -435,6 +437,9 @@ lkp_status lkp_group_remove(lkp_group *g, lkp_handle *h) {
   if (it == g->members.end()) return fail(LKP_ERR_ARG, "handle is not in this group");
   g->members.erase(it);
   h->group = nullptr;
+  // back to the handle's own split (cached chunk graphs are keyed by split)
+  h->split = h->solo_split;
+  h->tuned = h->solo_tuned;
   return LKP_OK;
 }
 

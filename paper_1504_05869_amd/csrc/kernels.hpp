@@ -184,9 +184,14 @@ hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, 
 // Elementwise helpers.
 hipError_t launch_f64_to_f32(const double *in, float *out, size_t n, hipStream_t s);
 
-// out[i n + x] = coef[i] phi0[x] for q planes of n cells (device pointers).
-hipError_t launch_equilibrium(const double *phi0, const double *coef, double *out, size_t n, int q,
-                              hipStream_t s);
+// Per-plane coefficients of an equilibrium state, passed by value.
+struct EqCoef {
+  double c[MAXQ];
+};
+// out plane j (n cells) = coef.c[j] * phi0 for j < q, as FP32 (fp32) or FP64;
+// phi0 and out are device pointers.
+hipError_t launch_equilibrium(const double *phi0, const EqCoef &coef, void *out, bool fp32, size_t n,
+                              int q, hipStream_t s);
 hipError_t launch_f32_to_f64(const float *in, double *out, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);

@@ -605,7 +605,9 @@ lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
 lkp_status run_chunk(lkp_handle *h, int k, bool use_graph) {
   if (h->scalar && h->total_sweeps == 0) use_graph = false;  // sweep 1 is a fill
   if (use_graph && k >= 2) {
-    const long key = (long)k * 2 + h->cur;
+    // the split is part of the key: a graph launches one split's kernels and
+    // its norm finish covers that split's blocks
+    const long key = ((long)k * 2 + h->cur) * 8 + h->split;
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
       if (!h->capture) HIP_TRY(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
@@ -1113,7 +1115,10 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
   const int64_t start = h->total_sweeps;
   lkp_status result = LKP_OK;
   if (lkp_status st = tune_split(h)) return st;
-  h->trk = Tracker();
+  // the convergence history of the plain sweep carries over from an earlier
+  // call on the same state, so a resumed solve measures its contraction
+  // across the calls (it is reset when the state is set or a group admits
+  // the handle)
 
   if (h->refined()) {
     if (!(o->tol_rel_l2 > 0)) return fail(LKP_ERR_ARG, "refinement (F32_IR, BF16DEV_IR) needs tol_rel_l2");
@@ -1408,6 +1413,7 @@ lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_
     HIP_TRY(hipFree(tmp));
     h->cur = 0;
     h->phi_sweep[0] = h->phi_sweep[1] = -1;
+    h->trk = Tracker();
     return LKP_OK;
   }
   const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1425,6 +1431,7 @@ lkp_status lkp_set_populations(lkp_handle *h, const double *src, int32_t src_is_
   }
   if (h->refined()) h->x_nonzero = true;  // a later solve refines this state
   h->phi_sweep[0] = h->phi_sweep[1] = -1;
+  h->trk = Tracker();
   return LKP_OK;
 }
 
@@ -1433,31 +1440,35 @@ lkp_status lkp_set_equilibrium(lkp_handle *h, const double *phi0, int32_t phi0_i
   if (h->scalar)
     return fail(LKP_ERR_UNSUPPORTED, "the tau_lb = 1 stencil form keeps Phi only; create the handle "
                                      "with LKP_FLAG_POPULATION_SWEEP to start from an equilibrium");
-  const size_t n = h->ncells, QN = (size_t)h->Q * n;
-  double *p0 = nullptr, *coef = nullptr, *f = nullptr;
-  auto release_tmp = [&]() {
-    if (p0) (void)hipFree(p0);
-    if (coef) (void)hipFree(coef);
-    if (f) (void)hipFree(f);
-  };
-  hipError_t e = hipMalloc(&p0, n * 8);
-  if (e == hipSuccess) e = hipMalloc(&coef, (size_t)h->Q * 8);
-  if (e == hipSuccess) e = hipMalloc(&f, QN * 8);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p0, phi0, n * 8, phi0_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                       h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(coef, h->phi.data(), (size_t)h->Q * 8, hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = launch_equilibrium(p0, coef, f, n, h->Q, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) {
-    release_tmp();
-    return fail(e == hipErrorOutOfMemory ? LKP_ERR_OOM : LKP_ERR_HIP, "lkp_set_equilibrium: %s",
-                hipGetErrorString(e));
+  const size_t n = h->ncells;
+  // a host field is staged through the handle's own Phi buffer (its contents
+  // are invalidated below anyway): no allocation
+  const double *p0 = phi0;
+  if (!phi0_is_device) {
+    HIP_TRY(hipMemcpyAsync(h->phib[0], phi0, n * 8, hipMemcpyHostToDevice, h->stream));
+    p0 = h->phib[0];
   }
-  const lkp_status st = lkp_set_populations(h, f, 1);
-  release_tmp();
-  return st;
+  // written straight into the state, in its precision and layout: plane j of
+  // the swapped in-place layout holds velocity opp(j)
+  const bool swapped = h->inplace && !h->refined();
+  EqCoef cf{};
+  if (swapped) {
+    const VelTable T = velocity_table(h->lattice);
+    const VelMaps M = build_maps(T);
+    for (int i = 0; i < h->Q; ++i) cf.c[M.vidx[6 - T.v[i][0]][6 - T.v[i][1]][6 - T.v[i][2]]] = h->phi[i];
+  } else {
+    for (int i = 0; i < h->Q; ++i) cf.c[i] = h->phi[i];
+  }
+  const bool fp32 = h->precision == LKP_F32;
+  void *out = h->refined() ? h->f[0] : h->f[swapped ? 0 : h->cur];
+  HIP_TRY(launch_equilibrium(p0, cf, out, fp32, n, h->Q, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (swapped) h->cur = 0;
+  if (h->refined()) h->x_nonzero = true;  // a later solve refines this state
+  h->phi_sweep[0] = h->phi_sweep[1] = -1;
+  h->trk = Tracker();
+  clear_error();
+  return LKP_OK;
 }
 
 lkp_status lkp_lattice_info(int32_t lattice, int32_t order, int32_t *Q, int32_t *dim, int32_t *v,

@@ -109,9 +109,12 @@ struct lkp_handle {
   int64_t footprint = 0;
   int split = 1;
   bool tuned = false;
+  int solo_split = 1;       // the handle's own split while a group imposes its own
+  bool solo_tuned = false;
   std::map<long, hipGraphExec_t> graphs;
 
-  // convergence state (reset at lkp_solve entry and at lkp_group_add)
+  // convergence state (kept across lkp_solve calls; reset when the state is
+  // set and at lkp_group_add)
   lkp::rt::Tracker trk;
   lkp::rt::IrState ir;
 

@@ -2,6 +2,8 @@
 // small utility kernels (norm finish, conversions, fills, IR update).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "lattices.hpp"
@@ -30,11 +32,15 @@ __global__ void k_f64_to_f32(const double *__restrict__ in, float *__restrict__ 
 }
 
 // f_i(x) = phi_i Phi_0(x) for every velocity plane i (grid-stride over Q n values)
-__global__ void k_equilibrium(const double *__restrict__ phi0, const double *__restrict__ coef,
-                              double *__restrict__ out, size_t n, size_t qn) {
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < qn;
-       k += (size_t)gridDim.x * blockDim.x)
-    out[k] = coef[k / n] * phi0[k % n];
+// Plane j of the state gets coef[j] * phi0 (FP64 product, stored in T).
+template <typename T>
+__global__ void __launch_bounds__(256) k_equilibrium(const double *__restrict__ phi0, EqCoef cf,
+                                                     T *__restrict__ out, size_t n) {
+  const double c = cf.c[blockIdx.y];
+  T *__restrict__ o = out + (size_t)blockIdx.y * n;
+  for (size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+       x += (size_t)gridDim.x * blockDim.x)
+    o[x] = (T)(c * phi0[x]);
 }
 
 __global__ void k_f32_to_f64(const float *__restrict__ in, double *__restrict__ out, size_t n) {
@@ -160,10 +166,15 @@ hipError_t launch_f64_to_f32(const double *in, float *out, size_t n, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_equilibrium(const double *phi0, const double *coef, double *out, size_t n, int q,
-                              hipStream_t s) {
-  const size_t qn = n * (size_t)q;
-  hipLaunchKernelGGL(k_equilibrium, dim3(grid_for(qn)), dim3(256), 0, s, phi0, coef, out, n, qn);
+hipError_t launch_equilibrium(const double *phi0, const EqCoef &coef, void *out, bool fp32, size_t n,
+                              int q, hipStream_t s) {
+  if (q < 1 || q > MAXQ) return hipErrorInvalidValue;
+  const unsigned gx = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+  const dim3 grid(gx ? gx : 1, (unsigned)q);
+  if (fp32)
+    hipLaunchKernelGGL(k_equilibrium<float>, grid, dim3(256), 0, s, phi0, coef, (float *)out, n);
+  else
+    hipLaunchKernelGGL(k_equilibrium<double>, grid, dim3(256), 0, s, phi0, coef, (double *)out, n);
   return hipGetLastError();
 }
 

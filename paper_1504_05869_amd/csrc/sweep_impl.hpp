@@ -16,7 +16,10 @@
 // velocities into P groups for the same 64-cell column, so each lane keeps
 // only ~Q/P populations in registers between the moment and the collision;
 // the partial moments meet in LDS.  P is chosen per (lattice, precision) by
-// the runtime's tuner.
+// the runtime's tuner.  The moment is always summed in the same order, so
+// every P gives the same bits: four fixed runs of ceil(Q/4) consecutive
+// velocities are summed in velocity order, then combined as
+// (s0 + s1) + (s2 + s3); a group of P = 2 holds two runs, P = 4 one.
 //
 // Blocks are renumbered so that runs of 16 consecutive blocks land on one XCD
 // (the hardware deals workgroups round-robin over the 8 XCDs): neighbouring
@@ -139,7 +142,9 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
   using TSRC = typename MT::TSRC;
   using TC = typename MT::TC;
   constexpr int Q = L::Q;
-  constexpr int QG = (Q + P - 1) / P;
+  constexpr int QS = (Q + 3) / 4;      // one of the four summation runs
+  constexpr int RUNS = 4 / P;          // runs per velocity group
+  constexpr int QG = QS * RUNS;        // velocities of a group (the last may hold fewer)
   constexpr int CELLS = 256 / P;
   constexpr int VMX = L::VMX, VMY = L::VMY, VMZ = L::VMZ;
 
@@ -188,8 +193,18 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
       const unsigned off = AA == 2 ? cc : (zw[vz + VMZ] * p.ny + yw[vy + VMY]) * p.nx + xw[vx + VMX];
       vals[i - lo] = ld<TIN>(fin + (size_t)li * plane * sizeof(TIN), off * (unsigned)sizeof(TIN));
     });
-    // moment in velocity order, FP64
-    static_for<lo, hi>([&](auto I) { part += (double)vals[(int)I - lo]; });
+    // moment, FP64: each run in velocity order, runs combined pairwise
+    double run[RUNS];
+    static_for<0, RUNS>([&](auto Rc) {
+      constexpr int R = decltype(Rc)::value;
+      constexpr int rlo = lo + R * QS < Q ? lo + R * QS : Q;
+      constexpr int rhi = rlo + QS < Q ? rlo + QS : Q;
+      run[R] = 0.0;
+      static_for<rlo, rhi>([&](auto I) { run[R] += (double)vals[(int)I - lo]; });
+    });
+    if constexpr (RUNS == 4) part = (run[0] + run[1]) + (run[2] + run[3]);
+    else if constexpr (RUNS == 2) part = run[0] + run[1];
+    else part = run[0];
     if constexpr (MT::POPSRC) {
       // correction sweeps: fold the population source in now, (1 - omega) f_i
       // + r_i, so that the r_i loads overlap the pulled loads instead of
@@ -217,9 +232,8 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
     __shared__ double sh[P][CELLS];
     sh[g][ci] = part;
     __syncthreads();
-    Phi = sh[0][ci];
-#pragma unroll
-    for (int k = 1; k < P; ++k) Phi += sh[k][ci];
+    if constexpr (P == 4) Phi = (sh[0][ci] + sh[1][ci]) + (sh[2][ci] + sh[3][ci]);
+    else Phi = sh[0][ci] + sh[1][ci];
   }
 
   const TC phic = (TC)Phi;

@@ -145,9 +145,10 @@ def test_group_rejects_drifted_handle():
         g.close()
 
 
-def test_drifted_bf16_deviation_sweeps_match_emulation():
+def test_drifted_bf16_deviation_sweeps_match_oracle():
     """BF16 deviation storage with a drifted equilibrium: the plain deviation
-    sweeps agree with the oracle's FP32 emulation of the same storage."""
+    sweeps agree with the oracle's BF16 storage of the same scheme (bound as
+    in tests/test_gpu_bf16dev.py: a quarter of the rounding effect)."""
     from oracle import bf16dev as B
     lattice, order, tau, shape, u = "D2Q81", 5, 2.5, (50, 70), (0.05, -0.03)
     s = W.zero_mean(np.random.default_rng(11).standard_normal(shape))
@@ -156,12 +157,13 @@ def test_drifted_bf16_deviation_sweeps_match_emulation():
         p.step(K)
         a = p.phi_host()
     prob = SW.Problem(lattice, order, tau, s, drift=u)
-    emu, _ = B.run(prob, K, S=prob.S.astype(np.float32), fp32_groups=2)  # D2Q81 split
+    orc, _ = B.run(prob, K)
     exact, _ = SW.run(prob, K)
-    say("bf16dev drift: identical", float(np.mean(a == emu)), "vs emulation", rel_l2(a, emu),
-        "BF16 effect", rel_l2(emu, exact))
-    assert float(np.mean(a == emu)) >= 0.999
-    assert rel_l2(a, emu) <= 1e-6 * rel_l2(emu, exact) + 1e-12
+    effect = rel_l2(orc, exact)
+    say("bf16dev drift: vs BF16 oracle", rel_l2(a, orc), "BF16 effect", effect)
+    assert effect > 1e-7
+    assert rel_l2(a, orc) <= 0.25 * effect
+    assert rel_l2(a, exact) <= 1.25 * effect
 
 
 def test_drifted_bf16_refinement_reaches_fixed_point():

@@ -98,7 +98,7 @@ def test_alone_equals_mix_bitwise(lattice, order, precision, split, specs):
         ref = SP.fixed_point(lattice, order, tau, _source(shape, seed))
         err = rel_l2(alone[k][0], ref)
         say("true error", shape, err)
-        assert err <= (1e-8 if precision == "f64" else 2e-7)
+        assert err <= 2 * tol
 
 
 def _group(lattice, order, precision, graphs):
@@ -230,5 +230,5 @@ def test_server_end_to_end_small_stream():
         ref = SP.fixed_point(q.lattice, q.order, tau, s)
         e_srv, e_base = rel_l2(r.phi, ref), rel_l2(b.phi, ref)
         say(q.shape, q.knudsen, "served err", e_srv, "baseline err", e_base)
-        assert e_srv <= 1e-6 and e_base <= 1e-6
+        assert e_srv <= 2e-7 and e_base <= 2e-7            # at most 2x the tolerance
     assert summ["peak_hbm_bytes"] <= 2 << 30

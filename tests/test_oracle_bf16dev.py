@@ -61,18 +61,30 @@ def test_rounding_is_active_and_small():
     assert np.array_equal(B.round_bf16(n), n)     # the stored deviations are BF16 values
 
 
-def test_fp32_evaluation_stays_close_to_fp64_evaluation():
-    """The FP32-arithmetic emulation (rounding decisions taken on FP32 values)
-    differs from the FP64 one only by rounding-decision flips: far less than
-    the BF16 effect itself; velocity grouping of the FP64 moment sum hardly
-    matters."""
-    s = W.zero_mean(np.random.default_rng(11).standard_normal((30, 40)))
+def test_rounding_stays_inside_its_envelope():
+    """One sweep from a common stored state: the new Phi carries one FP32
+    rounding, |dPhi| <= 2^-24 |Phi|, and each new deviation one BF16 rounding
+    of an argument that differs from the unrounded one only through that Phi,
+    so |dn_i| <= 2^-8 |n_i| + (1 + 2^-8) |1 - omega| |phi_i| |dPhi|.  Checked
+    value by value, and the unrounded sweep is the scheme's sweep of the
+    populations phi_i Phi + n_i."""
+    rng = np.random.default_rng(12)
+    s = W.zero_mean(rng.standard_normal((14, 18)))
     p = SW.Problem("D2Q81", 5, 2.5, s)
-    S32 = p.S.astype(np.float32)
-    a, _ = B.run(p, 9, S=S32, fp32_groups=1)
-    b, _ = B.run(p, 9, S=S32.astype(np.float64))
-    e, _ = SW.run(p, 9)
-    effect = np.linalg.norm(b - e) / np.linalg.norm(e)
-    assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 0.1 * effect
-    c, _ = B.run(p, 9, S=S32, fp32_groups=4)
-    assert np.linalg.norm(a - c) / np.linalg.norm(a) <= 1e-3 * effect
+    Phi0 = B.round_fp32(rng.standard_normal(p.shape))
+    n0 = B.round_bf16(0.1 * rng.standard_normal((p.lat.Q,) + p.shape))
+    n_r, Phi_r = B.sweep(p, n0, Phi0)
+    n_e, Phi_e = B.sweep(p, n0, Phi0, rounding=False)
+    u8, u24 = 2.0 ** -8, 2.0 ** -24
+    dPhi = np.abs(Phi_r - Phi_e)
+    assert np.all(dPhi <= u24 * np.abs(Phi_e))
+    bound = u8 * np.abs(n_e) + (1 + u8) * abs(1 - p.omega) * np.abs(p.phi)[:, None, None] * dPhi[None]
+    assert np.all(np.abs(n_r - n_e) <= bound * (1 + 1e-12))
+    assert np.any(n_r != n_e)                       # the rounding is active
+    # the inputs were already representable: the unrounded sweep's Phi is the
+    # scheme's Phi of the populations phi_i Phi0 + n0
+    f0 = p.phi[:, None, None] * Phi0[None] + n0
+    out = np.empty_like(f0)
+    Phi_c = np.empty(p.shape)
+    SW.sweep_c(p, np.ascontiguousarray(f0), out, Phi_c)
+    assert np.max(np.abs(Phi_c - Phi_e)) <= 1e-13 * np.max(np.abs(Phi_e))
