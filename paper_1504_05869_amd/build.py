@@ -11,12 +11,14 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblkp.so")
-LATTICES = ["d1q5", "d1q9", "d1q13", "d2q5", "d2q9", "d2q25", "d2q81", "d2q169", "d3q111",
-            "d2q37", "d2q77"]
-# largest first so the parallel build finishes early
-SOURCES = (["sweep_d2q169.hip", "sweep_d3q111.hip", "sweep_d2q81.hip"]
-           + [f"sweep_{l}.hip" for l in LATTICES if l not in ("d2q169", "d3q111", "d2q81")]
-           + ["sweep.hip", "dev.hip", "lkp.cpp", "group.cpp", "constants.cpp"])
+LATTICES = ["D2Q169", "D3Q111", "D2Q81", "D2Q77", "D2Q37", "D1Q13", "D2Q25", "D1Q9", "D2Q9",
+            "D1Q5", "D2Q5"]
+# (source, defines, object): every velocity set is compiled in five parts
+# (dispatch + stencil + deviation sweep, then one part per precision mode),
+# largest sets first so that the parallel build finishes early
+JOBS = ([("sweep_tu.hip", [f"-DLKP_TU_LATTICE={l}", f"-DLKP_TU_MODE={m}"], f"sweep_{l.lower()}_{m + 1}")
+         for l in LATTICES for m in (0, 1, 3, 2, -1)]
+        + [(src, [], src) for src in ("sweep.hip", "dev.hip", "lkp.cpp", "group.cpp", "constants.cpp")])
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -26,9 +28,10 @@ DEVICE = ["--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, defines, name = job
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC, *COMMON, *DEVICE, *defines, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     subprocess.check_call(cmd)
     return obj
 
@@ -37,7 +40,7 @@ def build(jobs: int = 8) -> str:
     """Compile every source for gfx950 and link liblkp.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(_compile, JOBS))
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs,
                            "-o", tmp])

@@ -19,7 +19,8 @@
 // the runtime's tuner.  The moment is always summed in the same order, so
 // every P gives the same bits: four fixed runs of ceil(Q/4) consecutive
 // velocities are summed in velocity order, then combined as
-// (s0 + s1) + (s2 + s3); a group of P = 2 holds two runs, P = 4 one.
+// (s0 + s1) + (s2 + s3); a group of P = 2 holds two runs, P = 4 one.  Sets of
+// at most 25 velocities (built for P = 1 only) sum in plain velocity order.
 //
 // Blocks are renumbered so that runs of 16 consecutive blocks land on one XCD
 // (the hardware deals workgroups round-robin over the 8 XCDs): neighbouring
@@ -142,8 +143,10 @@ __device__ __forceinline__ void sweep_block(const Params &p, unsigned blk, const
   using TSRC = typename MT::TSRC;
   using TC = typename MT::TC;
   constexpr int Q = L::Q;
-  constexpr int QS = (Q + 3) / 4;      // one of the four summation runs
-  constexpr int RUNS = 4 / P;          // runs per velocity group
+  constexpr int NRUNS = Q <= 25 ? 1 : 4;  // summation runs (small sets: one, in velocity order)
+  static_assert(NRUNS % P == 0, "a velocity group holds whole summation runs");
+  constexpr int QS = (Q + NRUNS - 1) / NRUNS;  // velocities of one run
+  constexpr int RUNS = NRUNS / P;      // runs per velocity group
   constexpr int QG = QS * RUNS;        // velocities of a group (the last may hold fewer)
   constexpr int CELLS = 256 / P;
   constexpr int VMX = L::VMX, VMY = L::VMY, VMZ = L::VMZ;
@@ -424,16 +427,6 @@ hipError_t launch_batch_mode(int P, int flags, const void *bp, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-template <int LID>
-hipError_t launch_batch_lattice(int mode, int P, int flags, const void *bp, hipStream_t s) {
-  switch (mode) {
-    case MODE_F64: return launch_batch_mode<LID, MODE_F64>(P, flags, bp, s);
-    case MODE_F32: return launch_batch_mode<LID, MODE_F32>(P, flags, bp, s);
-    case MODE_INNER: return launch_batch_mode<LID, MODE_INNER>(P, flags, bp, s);
-  }
-  return hipErrorInvalidValue;
-}
-
 template <int LID, int MODE>
 hipError_t launch_mode(int P, int aa, int flags, SweepParams p, hipStream_t s) {
   switch (P) {
@@ -450,27 +443,39 @@ hipError_t launch_mode(int P, int aa, int flags, SweepParams p, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+}  // namespace sweep_detail
+
+// Entry points of one (lattice, mode): each is compiled in a translation unit
+// of its own, so the large sets build in parallel.
+template <int LID, int MODE>
+hipError_t launch_mode_tu(int P, int aa, int flags, SweepParams p, hipStream_t s) {
+  return sweep_detail::launch_mode<LID, MODE>(P, aa, flags, p, s);
+}
+
+template <int LID, int MODE>
+hipError_t launch_batch_mode_tu(int P, int flags, const void *bp, hipStream_t s) {
+  return sweep_detail::launch_batch_mode<LID, MODE>(P, flags, bp, s);
+}
+
 template <int LID>
-hipError_t launch_lattice(int mode, int P, int aa, int flags, SweepParams p, hipStream_t s) {
+hipError_t launch_lattice_tu(int mode, int P, int aa, int flags, SweepParams p, hipStream_t s) {
   switch (mode) {
-    case MODE_F64: return launch_mode<LID, MODE_F64>(P, aa, flags, p, s);
-    case MODE_F32: return launch_mode<LID, MODE_F32>(P, aa, flags, p, s);
-    case MODE_RESID: return launch_mode<LID, MODE_RESID>(P, aa, flags, p, s);
-    case MODE_INNER: return launch_mode<LID, MODE_INNER>(P, aa, flags, p, s);
+    case MODE_F64: return launch_mode_tu<LID, MODE_F64>(P, aa, flags, p, s);
+    case MODE_F32: return launch_mode_tu<LID, MODE_F32>(P, aa, flags, p, s);
+    case MODE_RESID: return launch_mode_tu<LID, MODE_RESID>(P, aa, flags, p, s);
+    case MODE_INNER: return launch_mode_tu<LID, MODE_INNER>(P, aa, flags, p, s);
   }
   return hipErrorInvalidValue;
 }
 
-}  // namespace sweep_detail
-
-template <int LID>
-hipError_t launch_lattice_tu(int mode, int P, int aa, int flags, SweepParams p, hipStream_t s) {
-  return sweep_detail::launch_lattice<LID>(mode, P, aa, flags, p, s);
-}
-
 template <int LID>
 hipError_t launch_batch_tu(int mode, int P, int flags, const void *bp, hipStream_t s) {
-  return sweep_detail::launch_batch_lattice<LID>(mode, P, flags, bp, s);
+  switch (mode) {
+    case MODE_F64: return launch_batch_mode_tu<LID, MODE_F64>(P, flags, bp, s);
+    case MODE_F32: return launch_batch_mode_tu<LID, MODE_F32>(P, flags, bp, s);
+    case MODE_INNER: return launch_batch_mode_tu<LID, MODE_INNER>(P, flags, bp, s);
+  }
+  return hipErrorInvalidValue;  // residual sweeps are launched one problem at a time
 }
 
 }  // namespace lkp
