@@ -151,8 +151,10 @@ int64_t lkp_footprint_bytes(const lkp_problem_desc *d);
 
 typedef struct lkp_solve_opts {
   double tol_rel_l2;    /* > 0: stop when the estimated relative L2 distance of Phi to the
-                           fixed point, |dPhi| rho / (1 - rho) / |Phi| with rho the measured
-                           per-sweep contraction, is <= tol_rel_l2 */
+                           fixed point, |dPhi| rho / (1 - rho) / |Phi| with rho the largest
+                           of the last four per-sweep contractions measured between checks,
+                           is <= tol_rel_l2 (refinement: the last correction scaled by the
+                           residual's shrink since it) */
   double tol_maxchange; /* > 0: stop when max_x |Phi_t - Phi_{t-1}| < tol_maxchange */
   int64_t max_sweeps;   /* hard cap on sweeps done by this call (> 0) */
   int32_t check_every;  /* sweeps between convergence checks (>= 1) */
@@ -173,7 +175,7 @@ typedef struct lkp_solve_report {
   double phi_l2;         /* ||Phi||_2 */
   double mass;           /* sum_x Phi */
   double est_rel_err;    /* estimated relative L2 distance to the fixed point */
-  double rate;           /* measured per-sweep contraction rho */
+  double rate;           /* per-sweep contraction rho used by the estimate */
   double wall_s;         /* wall time of the call */
   double glups;          /* 1e-9 * cells * sweeps / wall_s */
 } lkp_solve_report;

@@ -130,7 +130,11 @@ lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
   if (!prev_ok) return LKP_OK;
   const double l2 = rep->l2_change;
   if (t.l2_prev > 0 && l2 > 0 && h->total_sweeps > t.t_prev) {
-    t.rate = std::pow(l2 / t.l2_prev, 1.0 / (double)(h->total_sweeps - t.t_prev));
+    t.rates[t.nrates % Tracker::kRates] =
+        std::pow(l2 / t.l2_prev, 1.0 / (double)(h->total_sweeps - t.t_prev));
+    t.nrates += 1;
+    t.rate = 0.0;
+    for (int j = 0; j < std::min(t.nrates, Tracker::kRates); ++j) t.rate = std::max(t.rate, t.rates[j]);
     rep->rate = t.rate;
   }
   if (l2 > 0) t.min_l2 = std::min(t.min_l2, l2);

@@ -32,10 +32,17 @@ double now_s();
 // Convergence bookkeeping of one problem across checks (Sec. 5: the answer is
 // the steady state; the host estimates the distance to it from the one-sweep
 // change and the measured contraction per sweep).
+// The contraction used for the estimate is the largest of the last four
+// measured between checks: where slow modes oscillate or are still emerging,
+// a single measurement can be well below the asymptotic rate, and the
+// estimate (1 / (1 - rho)) would stop early.
 struct Tracker {
+  static constexpr int kRates = 4;
   double l2_prev = -1.0;
   double min_l2 = 1e300;
-  double rate = 0.0;
+  double rate = 0.0;            // contraction used for the estimate
+  double rates[kRates] = {0, 0, 0, 0};  // last measured per-sweep contractions
+  int nrates = 0;
   int64_t t_prev = -1;
 };
 
