@@ -419,15 +419,14 @@ def extras_tts(lkp, torch, W) -> dict:
                             "phi_16_16": float(phi[16, 16]),
                             "note": "160 KB of populations: cache resident, launch bound"}
     # 256^3 D3Q111 N=5 at tau_lb = 1 (512 Gaussians + sine background): stencil
-    # form (F32_IR, FP64) and population sweep (F32_IR), to rel-L2 1e-6
+    # form, F32_IR and FP64, to rel-L2 1e-6 (the population sweep of the same
+    # problem takes about two minutes: --configs)
     s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
     ref3 = oracle_fixed_point("D3Q111", 5, s3, tau_lb=1.0)
     tts3 = []
     for prec in ("f32_ir", "f64"):
         tts3.append(dict(timed_solve(lkp, torch, s3, "D3Q111", 5, prec, 1e-6, ref=ref3, check_every=200,
                                      tau_lb=1.0), form="stencil (tau_lb=1)"))
-    tts3.append(dict(timed_solve(lkp, torch, s3, "D3Q111", 5, "f32_ir", 1e-6, ref=ref3, check_every=200,
-                                 tau_lb=1.0, population_sweep=True), form="population sweep"))
     out["time_to_solution_256cubed"] = tts3
     del s3, ref3
     # 1024^2 D2Q81 N=5 Kn=0.1: FP64, FP32 + refinement, BF16 deviation + refinement
@@ -459,8 +458,9 @@ def extras_tts(lkp, torch, W) -> dict:
 
 def configs_matrix(lkp, torch, W) -> dict:
     """The 1024^2 workload at every order and Knudsen number, FP64 and FP32 +
-    refinement, to rel-L2 1e-6 with true errors; the 256^3 BF16 deviation
-    ablation (population sweep, tau_lb = 1) as a separate run."""
+    refinement, to rel-L2 1e-6 with true errors; the 256^3 problem (tau_lb = 1)
+    solved by population sweeps, FP32 + refinement and the BF16 deviation
+    ablation as a separate run."""
     s = W.poisson_source("blobs2d", (1024, 1024), seed=12345)
     rows = []
     for N, lat in ORDERS.items():
@@ -507,6 +507,9 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="only the order x Knudsen x precision matrix of the 1024^2 workload and "
                          "the 256^3 BF16 ablation (a few minutes)")
+    ap.add_argument("--rates-only", action="store_true",
+                    help="only the per-sweep rates of the other sets, precisions and forms "
+                         "(counter runs of those kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -526,6 +529,9 @@ def main():
         return
     if args.configs:
         print(json.dumps({"configs": configs_matrix(lkp, torch, W)}), flush=True)
+        return
+    if args.rates_only:
+        print(json.dumps({"sweeps": extras_rates(lkp, torch, W)}), flush=True)
         return
     if args.calibrate_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
