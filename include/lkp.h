@@ -254,6 +254,29 @@ lkp_status lkp_get_coefficients(lkp_handle *h, double *phi, double *chi);
  * LKP_ERR_HIP. */
 lkp_status lkp_set_equilibrium(lkp_handle *h, const double *phi0, int32_t phi0_is_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the FP64
+ * residual sweep of lkp_residual for a population state held in caller-owned
+ * device buffers, with no handle and no allocation.  Its per-block partial
+ * norms use a fixed array in device memory (12 MiB per GPU, held until the
+ * process ends), so it serves grids of at most 2^24 cells (LKP_ERR_ARG
+ * beyond).  Everything is enqueued on `stream` (hipStream_t, NULL = default):
+ * two kernel launches, no copy, no synchronisation.  Calls on one GPU share
+ * that array: calls that overlap on one GPU (several streams, threads) race.
+ *   lattice, order, n[3], tau_lb: as in lkp_problem_desc (explicit tau_lb, no drift)
+ *   f:        Q*n FP64 post-collision populations (device, plane i = velocity i)
+ *   S:        n FP64 scaled source S = s c_s^2 (tau_lb - 1/2) (device)
+ *   phi_prev: n FP64 (device) Phi of the sweep that produced f, or NULL (zeros)
+ *   phi_out:  n FP64 (device) output: Phi of the next sweep (the moment of f streamed)
+ *   r_out:    Q*n FP32 (device) output: residual populations r = T f + g - f, or NULL
+ *   norms_out: 6 FP64 (device) output: max |Phi' - Phi_prev|, sum (Phi' - Phi_prev)^2,
+ *             sum Phi'^2, sum Phi', count of non-finite values, sum r^2 (lkp_residual
+ *             reports the square roots of the second, third and sixth).
+ * Errors (nothing is enqueued): LKP_ERR_ARG, LKP_ERR_LATTICE_ORDER, LKP_ERR_HIP. */
+lkp_status lkp_residual_noalloc(int32_t lattice, int32_t order, const int64_t n[3], double tau_lb,
+                                const double *f, const double *S, const double *phi_prev,
+                                double *phi_out, float *r_out, double *norms_out, void *stream);
+
 /* Wait for all of the handle's queued work. */
 lkp_status lkp_sync(lkp_handle *h);
 

@@ -109,6 +109,10 @@ def load() -> ctypes.CDLL:
         "lkp_get_coefficients": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_void_p]),
         "lkp_set_equilibrium": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_int32]),
         "lkp_sync": (ctypes.c_int, [H]),
+        "lkp_residual_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int64),
+                                                ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p]),
         "lkp_last_error": (ctypes.c_char_p, []),
         "lkp_group_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_void_p, P(H)]),

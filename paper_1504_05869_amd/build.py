@@ -18,7 +18,8 @@ LATTICES = ["D2Q169", "D3Q111", "D2Q81", "D2Q77", "D2Q37", "D1Q13", "D2Q25", "D1
 # largest sets first so that the parallel build finishes early
 JOBS = ([("sweep_tu.hip", [f"-DLKP_TU_LATTICE={l}", f"-DLKP_TU_MODE={m}"], f"sweep_{l.lower()}_{m + 1}")
          for l in LATTICES for m in (0, 1, 3, 2, -1)]
-        + [(src, [], src) for src in ("sweep.hip", "dev.hip", "lkp.cpp", "group.cpp", "constants.cpp")])
+        + [(src, [], src) for src in ("sweep.hip", "dev.hip", "lkp.cpp", "group.cpp", "constants.cpp",
+                                   "noalloc.cpp")])
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

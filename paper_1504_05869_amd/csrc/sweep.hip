@@ -31,7 +31,6 @@ __global__ void k_f64_to_f32(const double *__restrict__ in, float *__restrict__ 
     out[i] = (float)in[i];
 }
 
-// f_i(x) = phi_i Phi_0(x) for every velocity plane i (grid-stride over Q n values)
 // Plane j of the state gets coef[j] * phi0 (FP64 product, stored in T).
 template <typename T>
 __global__ void __launch_bounds__(256) k_equilibrium(const double *__restrict__ phi0, EqCoef cf,
