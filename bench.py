@@ -378,6 +378,10 @@ def extras_rates(lkp, torch, W) -> list:
     for prec in ("f32", "f64"):
         extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
                                       sweeps=40, population_sweep=True), grid="256^3"))
+        # the generated 3D set with 107 velocities, same problem
+        extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q107", 5, prec, tau_lb=1.0,
+                                      sweeps=40, population_sweep=True), grid="256^3",
+                           form="generated set"))
         extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
                                       sweeps=40, population_sweep=True, in_place=True),
                            grid="256^3"))
@@ -389,6 +393,12 @@ def extras_rates(lkp, torch, W) -> list:
              gbs=s.size * bpc_dev / (r["ms_per_sweep"] * 1e-3) / 1e9)
     r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
     extras.append(r)
+    # D3Q107 on the headline problem (512^3, Kn = 0.3, FP64, two buffers): the
+    # same sweep with 4 fewer velocities (the headline line is D3Q111)
+    s5 = W.poisson_source(C5["kind"], C5["shape"], seed=C5["seed"])
+    extras.append(dict(sweep_rate(lkp, torch, s5, "D3Q107", 5, "f64", knudsen=C5["knudsen"],
+                                  sweeps=20), grid="512^3", form="generated set"))
+    del s5
     # tau_lb = 1: the stencil form (state Phi, 3 values moved per cell)
     for prec in ("f32", "f64"):
         r = sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0, sweeps=200)

@@ -55,7 +55,9 @@ typedef enum lkp_status {
 
 /* Velocity sets.  1D sets: Appendix A.  2D: tensor products of the 1D sets
  * (the paper's "tensorial" extension, Sec. 4) and the standard
- * nearest-neighbour D2Q5 / D2Q9.  3D: D3Q111 (Appendix A, Table vector2). */
+ * nearest-neighbour D2Q5 / D2Q9.  3D: D3Q111 (Appendix A, Table vector2).
+ * Generated sets (quadrature conditions of Sec. 4, smallest stable): D2Q37,
+ * D2Q77, D3Q107. */
 typedef enum lkp_lattice {
   LKP_D1Q5 = 0,   /* N <= 3 */
   LKP_D1Q9 = 1,   /* N <= 5 */
@@ -68,7 +70,9 @@ typedef enum lkp_lattice {
   LKP_D3Q111 = 8, /* N <= 5 */
   LKP_D2Q37 = 9,  /* N <= 5: generated minimal 2D set (quadrature conditions of Sec. 4) */
   LKP_D2Q77 = 10, /* N <= 7: generated minimal 2D set stable at N = 7 */
-  LKP_NUM_LATTICES = 11
+  LKP_D3Q107 = 11, /* N <= 5: generated minimal 3D set stable at N = 5 (shells 0, (1,0,0),
+                      (1,1,0), (1,1,1), (2,0,0), (2,1,0), (2,2,0), (3,0,0), (3,1,1), (2,2,2)) */
+  LKP_NUM_LATTICES = 12
 } lkp_lattice;
 
 typedef enum lkp_precision {

@@ -11,7 +11,7 @@ import torch  # noqa: F401
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblkp.so")
 
 LATTICES = {"D1Q5": 0, "D1Q9": 1, "D1Q13": 2, "D2Q5": 3, "D2Q9": 4, "D2Q25": 5,
-            "D2Q81": 6, "D2Q169": 7, "D3Q111": 8, "D2Q37": 9, "D2Q77": 10}
+            "D2Q81": 6, "D2Q169": 7, "D3Q111": 8, "D2Q37": 9, "D2Q77": 10, "D3Q107": 11}
 PRECISIONS = {"f64": 0, "f32": 1, "f32_ir": 2, "bf16dev_ir": 3}
 STATUS = {0: "LKP_OK", 1: "LKP_ERR_ARG", 2: "LKP_ERR_LATTICE_ORDER", 3: "LKP_ERR_UNSTABLE",
           4: "LKP_ERR_SOURCE_MEAN", 5: "LKP_ERR_OOM", 6: "LKP_ERR_HIP",

@@ -16,9 +16,10 @@
 //          again under the label c_s^2)
 //   D3Q111 the value at which all eleven cubic moment classes of degree <= 8
 //          hold with ten shell weights (Table vector2 does not print it)
-//   D2Q37, D2Q77  generated shell sets (Sec. 4's systematic construction):
-//          the value at which all 9 (degree <= 8) resp. 16 (degree <= 12)
-//          square-symmetric moment classes hold with 8 resp. 15 shell weights
+//   D2Q37, D2Q77, D3Q107  generated shell sets (Sec. 4's systematic
+//          construction): the value at which all 9 (degree <= 8), 16 (degree
+//          <= 12) resp. 11 (degree <= 8) moment classes hold with 8, 15 resp.
+//          10 shell weights
 //   D2Q5, D2Q9  1/3 (standard nearest-neighbour sets)
 //
 // phi_i / w_i and chi_i / w_i in the radial Hermite polynomials of
@@ -296,7 +297,8 @@ bool lattice_constants(int id, LatticeConstants* out) {
     }
     return true;
   }
-  if (id == D3Q111 || id == D2Q37 || id == D2Q77) return shell_constants(T, &out->cs2, &out->w);
+  if (id == D3Q111 || id == D3Q107 || id == D2Q37 || id == D2Q77)
+    return shell_constants(T, &out->cs2, &out->w);
   Base1D b;
   ld t;
   if (!base_1d(id, &b, &t)) return false;

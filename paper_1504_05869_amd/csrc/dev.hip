@@ -66,6 +66,7 @@ hipError_t launch_dev(int lattice, bool inner, int flags, DevParams p, hipStream
     case D3Q111: return launch_dev_tu<D3Q111>(inner, flags, p, s);
     case D2Q37: return launch_dev_tu<D2Q37>(inner, flags, p, s);
     case D2Q77: return launch_dev_tu<D2Q77>(inner, flags, p, s);
+    case D3Q107: return launch_dev_tu<D3Q107>(inner, flags, p, s);
   }
   return hipErrorInvalidValue;
 }

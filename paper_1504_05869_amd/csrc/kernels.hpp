@@ -92,6 +92,7 @@ static_assert(sizeof(BatchParams<169>) <= 4096, "batched launch arguments exceed
 static_assert(sizeof(BatchParams<111>) <= 4096, "batched launch arguments exceed 4 KiB");
 static_assert(sizeof(BatchParams<5>) <= 4096, "batched launch arguments exceed 4 KiB");
 static_assert(sizeof(BatchParams<77>) <= 4096, "batched launch arguments exceed 4 KiB");
+static_assert(sizeof(BatchParams<107>) <= 4096, "batched launch arguments exceed 4 KiB");
 
 // ---- omega = 1: the sweep as a scalar stencil on Phi --------------------
 enum StencilMode : int {
@@ -137,9 +138,9 @@ unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz);
 inline unsigned cells_per_block(int P) { return 256u / (unsigned)P; }
 
 // The one split of the refinement's correction sweep (MODE_INNER), measured
-// fastest on MI355X: 1 up to 81 velocities, 2 for 111, 4 for 169.  FP32 first
+// fastest on MI355X: 1 up to 81 velocities, 2 for 107 and 111, 4 for 169.  FP32 first
 // solves of a refinement use the same split, so it is built for MODE_F32 too.
-constexpr int inner_split(int q) { return q >= 169 ? 4 : (q >= 111 ? 2 : 1); }
+constexpr int inner_split(int q) { return q >= 169 ? 4 : (q >= 100 ? 2 : 1); }
 
 // Velocity-group splits compiled per (lattice, mode): small sets P = 1; for
 // the large ones the candidates the tuner chooses between.

@@ -8,6 +8,7 @@
 //     D2Q5 and D2Q9 are the standard nearest-neighbour sets.
 //   3D: D3Q111 (Appendix A, Table vector2), ten shells of signed
 //     permutations, N <= 5.
+//   D3Q107: generated 3D set, the smallest shell set stable at N = 5.
 //   Generated 2D sets (Sec. 4's construction from the quadrature conditions:
 //     the smallest shell sets with positive weights reproducing every Gaussian
 //     moment to the needed degree, stable at their order):
@@ -19,7 +20,8 @@
 namespace lkp {
 
 enum LatticeId : int {
-  D1Q5 = 0, D1Q9, D1Q13, D2Q5, D2Q9, D2Q25, D2Q81, D2Q169, D3Q111, D2Q37, D2Q77, NUM_LATTICES
+  D1Q5 = 0, D1Q9, D1Q13, D2Q5, D2Q9, D2Q25, D2Q81, D2Q169, D3Q111, D2Q37, D2Q77, D3Q107,
+  NUM_LATTICES
 };
 
 constexpr int MAXQ = 169;
@@ -80,17 +82,25 @@ constexpr VelTable nearest(bool diagonals) {
 constexpr int SHELLS111[10][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {3, 3, 3}, {3, 3, 0},
                                   {3, 1, 0}, {2, 2, 0}, {2, 1, 1}, {2, 0, 0}, {3, 0, 0}};
 
-constexpr VelTable d3q111() {
+// Generated 3D set: the smallest shell set whose N = 5 scheme is stable
+// (Sec. 4's construction from the quadrature conditions, with the stability
+// the Appendix sets do not need to state): 107 velocities.
+constexpr int SHELLS107[10][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {1, 1, 1}, {2, 0, 0},
+                                  {2, 1, 0}, {2, 2, 0}, {3, 0, 0}, {3, 1, 1}, {2, 2, 2}};
+
+// 3D set from shell representatives: each shell's signed permutations, shell
+// after shell.
+constexpr VelTable shells_3d(const int (*sh)[3], int nshell, int max_order) {
   VelTable t{};
   const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
   int k = 0;
-  for (int s = 0; s < 10; ++s) {
+  for (int s = 0; s < nshell; ++s) {
     const int start = k;
     for (int p = 0; p < 6; ++p)
       for (int sg = 0; sg < 8; ++sg) {
         int c[3] = {0, 0, 0};
         for (int a = 0; a < 3; ++a) {
-          const int val = SHELLS111[s][perm[p][a]];
+          const int val = sh[s][perm[p][a]];
           c[a] = ((sg >> a) & 1) ? -val : val;
         }
         bool seen = false;
@@ -106,7 +116,7 @@ constexpr VelTable d3q111() {
   }
   t.q = k;
   t.dim = 3;
-  t.max_order = 5;
+  t.max_order = max_order;
   return t;
 }
 
@@ -155,7 +165,8 @@ constexpr VelTable velocity_table(int id) {
     case D2Q25: return detail::square(detail::S5, 5, 3);
     case D2Q81: return detail::square(detail::S9, 9, 5);
     case D2Q169: return detail::square(detail::S13, 13, 7);
-    case D3Q111: return detail::d3q111();
+    case D3Q111: return detail::shells_3d(detail::SHELLS111, 10, 5);
+    case D3Q107: return detail::shells_3d(detail::SHELLS107, 10, 5);
     case D2Q37: return detail::shells_2d(detail::SHELLS37, 8, 5);
     case D2Q77: return detail::shells_2d(detail::SHELLS77, 15, 7);
     default: return VelTable{};
@@ -253,6 +264,7 @@ static_assert(velocity_table(D2Q81).q == 81, "");
 static_assert(velocity_table(D2Q37).q == 37, "eight shells of 1, 4, 4, 4, 8, 4, 4, 8 velocities");
 static_assert(velocity_table(D2Q77).q == 77, "fifteen shells");
 static_assert(num_orbits(velocity_table(D3Q111)) == 10, "Table vector2 has ten weight classes");
+static_assert(velocity_table(D3Q107).q == 107, "ten shells of 1, 6, 12, 8, 6, 24, 12, 6, 24, 8");
 static_assert(num_orbits(velocity_table(D2Q169)) <= 32, "stencil weights travel in scalar registers");
 
 }  // namespace lkp

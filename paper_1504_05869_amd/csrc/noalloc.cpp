@@ -67,7 +67,9 @@ extern "C" lkp_status lkp_residual_noalloc(int32_t lattice, int32_t order, const
   for (int a = 0; a < 3; ++a) {
     if (n[a] < 1) return fail(LKP_ERR_ARG, "n[%d] = %lld < 1", a, (long long)n[a]);
     if (a >= T.dim && n[a] != 1) return fail(LKP_ERR_ARG, "n[%d] must be 1 for a %dD set", a, T.dim);
-    cells *= n[a];
+    if (n[a] > kMaxCells)
+      return fail(LKP_ERR_ARG, "lkp_residual_noalloc serves at most 2^24 cells (its scratch is fixed)");
+    cells *= n[a];  // both factors at most 2^24: no overflow
     if (cells > kMaxCells)
       return fail(LKP_ERR_ARG, "lkp_residual_noalloc serves at most 2^24 cells (its scratch is fixed)");
   }

@@ -12,13 +12,11 @@
 
 #include "kernels.hpp"
 #include "lkp.h"
+#include "validate.hpp"
 
 namespace lkp {
 namespace rt {
 
-lkp_status fail(lkp_status st, const char *fmt, ...);
-void clear_error();
-const char *last_error();
 double now_s();
 
 #define LKP_HIP_TRY(expr)                                                                     \

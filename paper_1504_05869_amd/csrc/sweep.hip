@@ -111,6 +111,7 @@ hipError_t launch_sweep(int lattice, int mode, int P, int flags, SweepParams p, 
     case D3Q111: return launch_lattice_tu<D3Q111>(mode, P, aa, flags, p, s);
     case D2Q37: return launch_lattice_tu<D2Q37>(mode, P, aa, flags, p, s);
     case D2Q77: return launch_lattice_tu<D2Q77>(mode, P, aa, flags, p, s);
+    case D3Q107: return launch_lattice_tu<D3Q107>(mode, P, aa, flags, p, s);
   }
   return hipErrorInvalidValue;
 }
@@ -129,6 +130,7 @@ hipError_t launch_sweep_batch(int lattice, int mode, int P, int flags, const voi
     case D3Q111: return launch_batch_tu<D3Q111>(mode, P, flags, bp, s);
     case D2Q37: return launch_batch_tu<D2Q37>(mode, P, flags, bp, s);
     case D2Q77: return launch_batch_tu<D2Q77>(mode, P, flags, bp, s);
+    case D3Q107: return launch_batch_tu<D3Q107>(mode, P, flags, bp, s);
   }
   return hipErrorInvalidValue;
 }
@@ -146,6 +148,7 @@ hipError_t launch_stencil(int lattice, int smode, int flags, const StencilParams
     case D3Q111: return launch_stencil_tu<D3Q111>(smode, flags, p, s);
     case D2Q37: return launch_stencil_tu<D2Q37>(smode, flags, p, s);
     case D2Q77: return launch_stencil_tu<D2Q77>(smode, flags, p, s);
+    case D3Q107: return launch_stencil_tu<D3Q107>(smode, flags, p, s);
   }
   return hipErrorInvalidValue;
 }

@@ -49,7 +49,8 @@ def check_against_bf16_oracle(a, prob, K, tag):
 
 @pytest.mark.parametrize("lattice,order,tau,shape", [
     ("D2Q25", 3, 3.0, (37, 66)), ("D2Q81", 5, 2.5, (50, 70)), ("D2Q169", 7, 4.0, (41, 77)),
-    ("D3Q111", 5, 1.7, (13, 19, 37)), ("D1Q13", 7, 3.0, (300,)), ("D2Q81", 5, 6.0, (3, 130))])
+    ("D3Q111", 5, 1.7, (13, 19, 37)), ("D1Q13", 7, 3.0, (300,)), ("D2Q81", 5, 6.0, (3, 130)),
+    ("D3Q107", 5, 2.2, (12, 15, 21))])
 def test_plain_deviation_sweeps_match_oracle(lattice, order, tau, shape):
     """K plain sweeps with BF16 deviation storage from rest (lkp_step on a
     bf16dev_ir handle) against the oracle's BF16 storage of the same scheme."""

@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 SETS = {"D1Q13": (7, (300,)), "D2Q5": (1, (45, 70)), "D2Q9": (3, (33, 40)),
         "D2Q25": (3, (37, 66)), "D2Q81": (5, (50, 70)), "D2Q169": (7, (41, 77)),
-        "D3Q111": (5, (13, 19, 37)), "D2Q37": (5, (43, 50)), "D2Q77": (7, (39, 66))}
+        "D3Q111": (5, (13, 19, 37)), "D2Q37": (5, (43, 50)), "D2Q77": (7, (39, 66)),
+        "D3Q107": (5, (11, 17, 29))}
 
 
 def say(*a):

@@ -15,11 +15,11 @@ from oracle import sweep as SW
 pytestmark = pytest.mark.gpu
 
 ORDER = {"D1Q5": 3, "D1Q9": 5, "D1Q13": 7, "D2Q5": 1, "D2Q9": 3, "D2Q25": 3, "D2Q81": 5,
-         "D2Q169": 7, "D3Q111": 5, "D2Q37": 5, "D2Q77": 7}
+         "D2Q169": 7, "D3Q111": 5, "D2Q37": 5, "D2Q77": 7, "D3Q107": 5}
 # ragged shapes spanning several 256-cell blocks (numpy order: (nz,) ny, nx)
 SHAPES = {"D1Q5": (333,), "D1Q9": (301,), "D1Q13": (257,), "D2Q5": (23, 37), "D2Q9": (23, 37),
           "D2Q25": (29, 41), "D2Q81": (31, 45), "D2Q169": (27, 33), "D3Q111": (9, 11, 13),
-          "D2Q37": (29, 35), "D2Q77": (33, 28)}
+          "D2Q37": (29, 35), "D2Q77": (33, 28), "D3Q107": (11, 9, 14)}
 
 
 def say(*a):
@@ -72,7 +72,7 @@ def test_k_sweep_parity_f64(lattice):
 @pytest.mark.parametrize("lattice,split", [("D2Q81", 1), ("D2Q81", 2), ("D2Q169", 2),
                                            ("D2Q169", 4), ("D3Q111", 2), ("D3Q111", 4),
                                            ("D2Q37", 1), ("D2Q37", 2), ("D2Q77", 1),
-                                           ("D2Q77", 2)])
+                                           ("D2Q77", 2), ("D3Q107", 2), ("D3Q107", 4)])
 def test_k_sweep_parity_every_split_f64(lattice, split):
     e_phi, e_pop, groups = k_sweep_case(lattice, SHAPES[lattice], 2.0, 4, split=split)
     assert groups == split
@@ -81,7 +81,8 @@ def test_k_sweep_parity_every_split_f64(lattice, split):
 
 @pytest.mark.parametrize("lattice,shape", [("D2Q169", (4, 5)), ("D3Q111", (2, 3, 2)),
                                            ("D1Q13", (4,)), ("D2Q81", (1, 7)), ("D2Q25", (1, 1)),
-                                           ("D2Q77", (3, 2)), ("D2Q37", (1, 5))])
+                                           ("D2Q77", (3, 2)), ("D2Q37", (1, 5)),
+                                           ("D3Q107", (3, 2, 2))])
 def test_grids_smaller_than_velocities(lattice, shape):
     """Axes shorter than the largest velocity wrap several times."""
     e_phi, e_pop, _ = k_sweep_case(lattice, shape, 1.5, 3)
@@ -90,7 +91,8 @@ def test_grids_smaller_than_velocities(lattice, shape):
 
 @pytest.mark.parametrize("lattice,split", [("D2Q81", 1), ("D2Q169", 1), ("D2Q169", 2),
                                            ("D3Q111", 1), ("D3Q111", 2), ("D2Q25", 1),
-                                           ("D2Q37", 1), ("D2Q77", 1)])
+                                           ("D2Q37", 1), ("D2Q77", 1), ("D3Q107", 1),
+                                           ("D3Q107", 2)])
 def test_k_sweep_parity_f32(lattice, split):
     e_phi, e_pop, _ = k_sweep_case(lattice, SHAPES[lattice], 1.3, 5, precision="f32",
                                    split=split)
@@ -105,7 +107,7 @@ def _blobs(shape, seed=3):
 @pytest.mark.parametrize("lattice,shape,tau", [("D2Q81", (40, 48), 2.0), ("D2Q169", (36, 30), 1.0),
                                                ("D2Q25", (50, 44), 5.0), ("D3Q111", (10, 12, 16), 1.0),
                                                ("D1Q13", (96,), 1.0), ("D2Q37", (40, 36), 1.0),
-                                               ("D2Q77", (36, 44), 2.0)])
+                                               ("D2Q77", (36, 44), 2.0), ("D3Q107", (12, 10, 14), 1.3)])
 def test_converged_f64_matches_spectral(lattice, shape, tau):
     say("converged f64", lattice, shape, tau)
     s = _blobs(shape)
@@ -136,7 +138,8 @@ def test_config1_stop_rule_matches_oracle():
 
 
 @pytest.mark.parametrize("lattice,shape,tau", [("D2Q81", (48, 64), 4.0), ("D3Q111", (12, 10, 16), 1.0),
-                                               ("D2Q169", (40, 36), 9.0), ("D2Q37", (48, 40), 3.0)])
+                                               ("D2Q169", (40, 36), 9.0), ("D2Q37", (48, 40), 3.0),
+                                               ("D3Q107", (14, 12, 10), 2.0)])
 def test_f32_ir_reaches_fp64_accuracy(lattice, shape, tau):
     say("f32-ir", lattice, shape, tau)
     s = _blobs(shape, seed=5)

@@ -13,10 +13,10 @@ from oracle import sweep as SW
 pytestmark = pytest.mark.gpu
 
 ORDER = {"D1Q13": 7, "D2Q5": 1, "D2Q9": 3, "D2Q25": 3, "D2Q81": 5, "D2Q169": 7, "D3Q111": 5,
-         "D2Q37": 5, "D2Q77": 7}
+         "D2Q37": 5, "D2Q77": 7, "D3Q107": 5}
 SHAPES = {"D1Q13": (300,), "D2Q5": (45, 70), "D2Q9": (33, 40), "D2Q25": (37, 66),
           "D2Q81": (50, 70), "D2Q169": (41, 77), "D3Q111": (13, 19, 37),
-          "D2Q37": (43, 50), "D2Q77": (39, 66)}
+          "D2Q37": (43, 50), "D2Q77": (39, 66), "D3Q107": (11, 21, 35)}
 
 
 def say(*a):

@@ -122,7 +122,7 @@ def _accepted(lattice, order, tau):
     return lib.lkp_footprint_bytes(ctypes.byref(d)) > 0
 
 
-@pytest.mark.parametrize("lattice,order", [("D2Q81", 5), ("D2Q37", 5), ("D3Q111", 5),
+@pytest.mark.parametrize("lattice,order", [("D2Q81", 5), ("D2Q37", 5), ("D3Q111", 5), ("D3Q107", 5),
                                            ("D2Q169", 7), ("D2Q77", 7), ("D1Q9", 5),
                                            ("D1Q13", 7)])
 def test_product_stability_limits_are_stable(lattice, order):
