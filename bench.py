@@ -73,6 +73,7 @@ def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=No
             "gbs": n * bpc / (ms * 1e-3) / 1e9,
             "frac_hbm": n * bpc / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "velocity_groups": info["velocity_groups"], "tau_lb": info["tau_lb"],
+            "stencil_tile": info["stencil_tile"], "stencil_remap": info["stencil_remap"],
             "form": "stencil (tau_lb=1)" if info["scalar_stencil"] else
                     ("population sweep, in place" if in_place else "population sweep")}
 

@@ -64,7 +64,8 @@ class HandleInfo(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("order", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("Q", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("velocity_groups", ctypes.c_int32), ("scalar_stencil", ctypes.c_int32),
-                ("in_place", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("in_place", ctypes.c_int32), ("stencil_tile", ctypes.c_int32),
+                ("stencil_remap", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
                 ("tau_lb", ctypes.c_double), ("omega", ctypes.c_double),
                 ("cs2", ctypes.c_double), ("total_sweeps", ctypes.c_int64),
                 ("footprint_bytes", ctypes.c_int64)]

@@ -13,11 +13,12 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblkp.so")
 LATTICES = ["D2Q169", "D3Q111", "D3Q107", "D2Q81", "D2Q77", "D2Q37", "D1Q13", "D2Q25", "D1Q9", "D2Q9",
             "D1Q5", "D2Q5"]
-# (source, defines, object): every velocity set is compiled in five parts
-# (dispatch + stencil + deviation sweep, then one part per precision mode),
+# (source, defines, object): every velocity set is compiled in eight parts
+# (dispatch + deviation sweep, one part per population-sweep precision mode,
+# one per stencil-form mode),
 # largest sets first so that the parallel build finishes early
 JOBS = ([("sweep_tu.hip", [f"-DLKP_TU_LATTICE={l}", f"-DLKP_TU_MODE={m}"], f"sweep_{l.lower()}_{m + 1}")
-         for l in LATTICES for m in (0, 1, 3, 2, -1)]
+         for l in LATTICES for m in (0, 1, 3, 10, 11, 2, 12, -1)]
         + [(src, [], src) for src in ("sweep.hip", "dev.hip", "lkp.cpp", "group.cpp", "constants.cpp",
                                    "noalloc.cpp", "validate.cpp")])
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -108,6 +108,9 @@ struct StencilParams {
   double *partials;  // NUM_NORMS per block (FLAG_REDUCE)
   unsigned nx, ny, nz;
   unsigned simple_wrap;
+  unsigned tile;     // 3D tile variant (stencil_tile_shape); 1D / 2D: 0
+  unsigned remap;    // 3D block order: 0 hardware, R > 0 runs of R blocks per XCD
+  unsigned gbx, gby; // 3D: blocks along x and y (set by the launcher)
   union {            // stencil weights per velocity orbit (phi, or chi to form G)
     double d[MAXQ];
     float f[MAXQ];
@@ -115,14 +118,26 @@ struct StencilParams {
 };
 
 // Output cells of one stencil block (256 threads): 1D 256; 2D 64 x 16;
-// 3D 64 x 8 x 32 (the block marches through its 32 z-planes).
+// 3D 64 x (4 CY) x BZ, the block marching through its BZ z-planes, with
+// (CY, BZ) one of the built tile variants.  The accumulation order of every
+// output cell is the same in every variant (input planes in z order, then x
+// offsets, then y offsets), so the variants give the same bits.
 struct StencilShape {
   unsigned tx, ty, tz;
 };
-constexpr StencilShape stencil_shape(int dim) {
-  return dim == 1 ? StencilShape{256, 1, 1} : (dim == 2 ? StencilShape{64, 16, 1} : StencilShape{64, 8, 32});
+constexpr int kStencilTiles3 = 6;
+constexpr int kStencilCY[kStencilTiles3] = {2, 2, 2, 4, 4, 1};
+constexpr int kStencilBZ[kStencilTiles3] = {32, 16, 8, 16, 8, 16};
+constexpr StencilShape stencil_tile_shape(int dim, int tile) {
+  return dim == 1 ? StencilShape{256, 1, 1}
+                  : (dim == 2 ? StencilShape{64, 16, 1}
+                              : StencilShape{64, 4u * (unsigned)kStencilCY[tile], (unsigned)kStencilBZ[tile]});
 }
+// Number of tile variants built for a dimension.
+constexpr int stencil_tiles(int dim) { return dim == 3 ? kStencilTiles3 : 1; }
 
+template <int LID, int SM>
+hipError_t launch_stencil_mode_tu(int flags, const StencilParams &p, hipStream_t s);
 template <int LID>
 hipError_t launch_stencil_tu(int smode, int flags, const StencilParams &p, hipStream_t s);
 
@@ -130,8 +145,10 @@ hipError_t launch_stencil_tu(int smode, int flags, const StencilParams &p, hipSt
 // the block norms of Phi' - Phi (or of R).
 hipError_t launch_stencil(int lattice, int smode, int flags, const StencilParams &p, hipStream_t s);
 
-// Blocks of a stencil launch on an nx x ny x nz grid.
-unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz);
+// Blocks of a stencil launch on an nx x ny x nz grid with a tile variant;
+// stencil_blocks_max: the most over the variants (partial-norm capacity).
+unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz, int tile);
+unsigned stencil_blocks_max(int lattice, unsigned nx, unsigned ny, unsigned nz);
 
 // Cells one block covers for a velocity-group split P (256 threads = 4 waves;
 // P waves share one 64-cell column and each holds Q/P populations).

@@ -37,6 +37,7 @@ namespace {
 // Process-wide choice of the velocity-group split per (lattice, mode, size class).
 std::mutex g_tune_mu;
 std::map<long, int> g_tune;
+std::map<long, std::pair<int, unsigned>> g_stile;  // 3D stencil: (tile, block order)
 
 long tune_key(int lattice, int mode, int64_t ncells) {
   int cls = 0;
@@ -159,6 +160,8 @@ lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
     p.nz = (unsigned)h->n[2];
     p.simple_wrap = h->simple_wrap ? 1u : 0u;
     p.partials = h->partials;
+    p.tile = (unsigned)h->stile;
+    p.remap = h->sremap;
     const VelTable T = velocity_table(h->lattice);
     const VelMaps M = build_maps(T);
     for (int i = 0; i < T.q; ++i) p.coef.d[M.orbit[i]] = h->phi[i];
@@ -168,7 +171,7 @@ lkp_status ir_launch_residual(lkp_handle *h, double *dst_dev) {
     hipError_t e = launch_stencil(h->lattice, SMODE_RESID, FLAG_REDUCE, p, h->stream);
     if (e != hipSuccess) return fail(LKP_ERR_HIP, "residual stencil launch: %s", hipGetErrorString(e));
     h->total_sweeps += 1;
-    return finish_norms(h, stencil_blocks(h->lattice, p.nx, p.ny, p.nz), dst_dev, h->stream);
+    return finish_norms(h, stencil_blocks(h->lattice, p.nx, p.ny, p.nz, h->stile), dst_dev, h->stream);
   }
   const int P = default_split(h->Q, MODE_RESID);
   SweepParams p = base_params(h);
@@ -505,7 +508,7 @@ lkp_status scalar_sweep(lkp_handle *h, hipStream_t s, int64_t t, int in, int out
 }
 
 unsigned scalar_blocks(const lkp_handle *h) {
-  return stencil_blocks(h->lattice, (unsigned)h->n[0], (unsigned)h->n[1], (unsigned)h->n[2]);
+  return stencil_blocks(h->lattice, (unsigned)h->n[0], (unsigned)h->n[1], (unsigned)h->n[2], h->stile);
 }
 
 // Enqueue a chunk of k >= 1 sweeps whose last sweep reduces norms (and, for
@@ -634,7 +637,81 @@ StencilParams stencil_params(const lkp_handle *h) {
   p.nz = (unsigned)h->n[2];
   p.simple_wrap = h->simple_wrap ? 1u : 0u;
   p.partials = h->partials;
+  p.tile = (unsigned)h->stile;
+  p.remap = h->sremap;
   return p;
+}
+
+// Pick the 3D stencil's tile variant and block order by timing each
+// candidate on the handle's own buffers (a few sweeps from the current Phi
+// into the idle buffer: the state is unchanged).  Every variant gives the
+// same bits, so the choice only moves the time.  Cached per process and
+// (set, mode, size class); LKP_STENCIL_TILE / LKP_STENCIL_REMAP force a
+// choice, LKP_AUTOTUNE=0 keeps the default.
+lkp_status tune_stencil(lkp_handle *h) {
+  if (h->dim != 3) return LKP_OK;
+  const char *ft = std::getenv("LKP_STENCIL_TILE");
+  const char *fr = std::getenv("LKP_STENCIL_REMAP");
+  if (ft || fr) {
+    if (ft) h->stile = std::max(0, std::min(kStencilTiles3 - 1, std::atoi(ft)));
+    if (fr) h->sremap = (unsigned)std::max(0, std::atoi(fr));
+    return LKP_OK;
+  }
+  const char *off = std::getenv("LKP_AUTOTUNE");
+  if ((off && std::atoi(off) == 0) || h->ncells < (1u << 18)) return LKP_OK;
+  const bool fp32 = h->precision != LKP_F64;
+  const long key = tune_key(h->lattice, 16 + (fp32 ? 1 : 0), h->ncells);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_stile.find(key);
+    if (it != g_stile.end()) {
+      h->stile = it->second.first;
+      h->sremap = it->second.second;
+      return LKP_OK;
+    }
+  }
+  StencilParams p = stencil_params(h);
+  stencil_weights(h, fp32, &p);
+  if (h->precision == LKP_F32_IR) {
+    p.xin = h->d32[0];
+    p.xout = h->d32[1];
+    p.src = h->S32;
+  } else {
+    p.xin = h->f[h->cur];
+    p.xout = h->f[1 - h->cur];
+    p.src = h->S;
+  }
+  const int smode = fp32 ? SMODE_F32 : SMODE_F64;
+  hipEvent_t e0, e1;
+  LKP_HIP_TRY(hipEventCreate(&e0));
+  LKP_HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bt = 0;
+  unsigned br = 0;
+  for (int t = 0; t < kStencilTiles3; ++t)
+    for (unsigned r : {0u, 4u, 16u}) {
+      p.tile = (unsigned)t;
+      p.remap = r;
+      LKP_HIP_TRY(launch_stencil(h->lattice, smode, 0, p, h->stream));
+      LKP_HIP_TRY(hipEventRecord(e0, h->stream));
+      for (int k = 0; k < 3; ++k) LKP_HIP_TRY(launch_stencil(h->lattice, smode, 0, p, h->stream));
+      LKP_HIP_TRY(hipEventRecord(e1, h->stream));
+      LKP_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      LKP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bt = t;
+        br = r;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->stile = bt;
+  h->sremap = br;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_stile[key] = {bt, br};
+  return LKP_OK;
 }
 
 // Per-orbit stencil weights from per-velocity values (equal on an orbit).
@@ -657,7 +734,7 @@ void stencil_weights(const lkp_handle *h, bool fp32, StencilParams *p) {
 unsigned partial_blocks(int lattice, const int64_t n[3]) {
   const unsigned ncells = (unsigned)(n[0] * n[1] * n[2]);
   const unsigned a = (ncells + cells_per_block(4) - 1) / cells_per_block(4);
-  const unsigned b = stencil_blocks(lattice, (unsigned)n[0], (unsigned)n[1], (unsigned)n[2]);
+  const unsigned b = stencil_blocks_max(lattice, (unsigned)n[0], (unsigned)n[1], (unsigned)n[2]);
   return std::max(a, b) + 8;
 }
 
@@ -738,7 +815,7 @@ lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::ve
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->split = 1;
   h->tuned = true;
-  return LKP_OK;
+  return tune_stencil(h);
 }
 
 lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
@@ -1450,6 +1527,8 @@ lkp_status lkp_get_info(lkp_handle *h, lkp_handle_info *info) {
   info->velocity_groups = h->split;
   info->scalar_stencil = h->scalar ? 1 : 0;
   info->in_place = h->inplace ? 1 : 0;
+  info->stencil_tile = h->scalar && h->dim == 3 ? h->stile : -1;
+  info->stencil_remap = h->scalar && h->dim == 3 ? (int32_t)h->sremap : -1;
   for (int a = 0; a < 3; ++a) info->n[a] = h->n[a];
   info->tau_lb = h->tau_lb;
   info->omega = h->omega;

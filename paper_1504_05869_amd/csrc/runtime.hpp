@@ -114,6 +114,8 @@ struct lkp_handle {
   int64_t footprint = 0;
   int split = 1;
   bool tuned = false;
+  int stile = 0;            // 3D stencil form: tile variant and block order (tune_stencil)
+  unsigned sremap = 0;
   int solo_split = 1;       // the handle's own split while a group imposes its own
   bool solo_tuned = false;
   std::map<long, hipGraphExec_t> graphs;

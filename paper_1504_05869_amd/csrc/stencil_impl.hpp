@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(256) k_stencil(StencilParams p) {
 }
 
 // 3D: a block owns a 64 x (4 CY) column of cells and marches through BZ
-// output planes.  Each input plane, with its x-y halo, is staged in LDS once
+// output planes ((CY, BZ) one of the tile variants the runtime times).  Each input plane, with its x-y halo, is staged in LDS once
 // and every staged value is pushed into the accumulators of all output planes
 // that use it (z = z_in + vz for |vz| <= VMZ), which live in a register ring
 // of 2 VMZ + 1 planes x CY rows.  Output plane m is complete once input plane
@@ -185,9 +185,7 @@ __global__ void __launch_bounds__(256) k_stencil(StencilParams p) {
 // while the current one is consumed, and the products are fused
 // multiply-adds.  For D3Q111 with CY = 2 an output cell costs 26 LDS reads
 // (72.5 when a whole 32 x 8 x 4 tile plus halo is staged and read per
-// z-offset) and staging reads 1.9 input values per output (5.2).  CY = 2 and
-// 32 planes per block measured fastest among CY in {2, 4, 6} and 8 to 32
-// planes, at 256^3 and 512^3.
+// z-offset) and staging reads 1.9 input values per output (5.2).
 template <int SM> struct FmaT;
 template <> struct FmaT<SMODE_F64> {
   static __device__ __forceinline__ double f(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -248,7 +246,13 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
   __shared__ TIN tile[2][NL];
 
   const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
-  const int x0 = (int)blockIdx.x * TX, y0 = (int)blockIdx.y * TY, z0 = (int)blockIdx.z * BZ;
+  // one linear grid; p.remap > 0 deals runs of p.remap consecutive blocks
+  // (neighbours along x, then y) to one XCD, so the halos they share meet
+  // in that XCD's L2
+  const unsigned nb = gridDim.x;
+  const unsigned lin = p.remap ? xcd_runs(blockIdx.x, nb, p.remap) : blockIdx.x;
+  const unsigned bxi = lin % p.gbx, byi = (lin / p.gbx) % p.gby, bzi = lin / (p.gbx * p.gby);
+  const int x0 = (int)bxi * TX, y0 = (int)byi * TY, z0 = (int)bzi * BZ;
   const unsigned pcells = (unsigned)nx * (unsigned)ny;
   const TIN *__restrict__ xin = reinterpret_cast<const TIN *>(p.xin);
 
@@ -371,43 +375,67 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
       }
     });
   }
-  if constexpr ((FLAGS & FLAG_REDUCE) != 0) {
-    const unsigned blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_norms(v, p.partials + (size_t)blk * NUM_NORMS);
-  }
+  if constexpr ((FLAGS & FLAG_REDUCE) != 0) block_norms(v, p.partials + (size_t)lin * NUM_NORMS);
+}
+
+template <int LID, int SM, int TILE>
+hipError_t launch_tile3(int flags, StencilParams p, hipStream_t s) {
+  constexpr int CY = kStencilCY[TILE], BZ = kStencilBZ[TILE];
+  constexpr StencilShape sh = stencil_tile_shape(3, TILE);
+  p.gbx = (p.nx + sh.tx - 1) / sh.tx;
+  p.gby = (p.ny + sh.ty - 1) / sh.ty;
+  const unsigned gbz = (p.nz + sh.tz - 1) / sh.tz;
+  const dim3 grid(p.gbx * p.gby * gbz);
+  if (flags & FLAG_REDUCE)
+    hipLaunchKernelGGL((k_stencil3<LID, SM, FLAG_REDUCE, CY, BZ>), grid, dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_stencil3<LID, SM, 0, CY, BZ>), grid, dim3(256), 0, s, p);
+  return hipGetLastError();
 }
 
 template <int LID, int SM>
 hipError_t launch_smode(int flags, const StencilParams &p, hipStream_t s) {
   constexpr int DIM = Lattice<LID>::DIM;
-  constexpr StencilShape sh = stencil_shape(DIM);
-  dim3 grid((p.nx + sh.tx - 1) / sh.tx, (p.ny + sh.ty - 1) / sh.ty, (p.nz + sh.tz - 1) / sh.tz);
   if constexpr (DIM == 3) {
-    static_assert(sh.tx == 64 && sh.ty % 4 == 0, "3D stencil tile: 64 x 4 CY");
-    constexpr int CY = sh.ty / 4, BZ = sh.tz;
-    if (flags & FLAG_REDUCE)
-      hipLaunchKernelGGL((k_stencil3<LID, SM, FLAG_REDUCE, CY, BZ>), grid, dim3(256), 0, s, p);
-    else
-      hipLaunchKernelGGL((k_stencil3<LID, SM, 0, CY, BZ>), grid, dim3(256), 0, s, p);
+    static_assert(kStencilTiles3 == 6, "one case per tile variant");
+    switch (p.tile) {
+      case 0: return launch_tile3<LID, SM, 0>(flags, p, s);
+      case 1: return launch_tile3<LID, SM, 1>(flags, p, s);
+      case 2: return launch_tile3<LID, SM, 2>(flags, p, s);
+      case 3: return launch_tile3<LID, SM, 3>(flags, p, s);
+      case 4: return launch_tile3<LID, SM, 4>(flags, p, s);
+      case 5: return launch_tile3<LID, SM, 5>(flags, p, s);
+    }
+    return hipErrorInvalidValue;
   } else {
     using T = Tile<DIM>;
+    constexpr StencilShape sh = stencil_tile_shape(DIM, 0);
     static_assert(T::TX == sh.tx && T::TY == sh.ty && T::TZ == sh.tz, "stencil tile");
+    if (p.tile != 0) return hipErrorInvalidValue;
+    dim3 grid((p.nx + sh.tx - 1) / sh.tx, (p.ny + sh.ty - 1) / sh.ty, (p.nz + sh.tz - 1) / sh.tz);
     if (flags & FLAG_REDUCE)
       hipLaunchKernelGGL((k_stencil<LID, SM, FLAG_REDUCE>), grid, dim3(256), 0, s, p);
     else
       hipLaunchKernelGGL((k_stencil<LID, SM, 0>), grid, dim3(256), 0, s, p);
+    return hipGetLastError();
   }
-  return hipGetLastError();
 }
 
 }  // namespace stencil_detail
 
+// One precision mode of the stencil form, compiled in a translation unit of
+// its own.
+template <int LID, int SM>
+hipError_t launch_stencil_mode_tu(int flags, const StencilParams &p, hipStream_t s) {
+  return stencil_detail::launch_smode<LID, SM>(flags, p, s);
+}
+
 template <int LID>
 hipError_t launch_stencil_tu(int smode, int flags, const StencilParams &p, hipStream_t s) {
   switch (smode) {
-    case SMODE_F64: return stencil_detail::launch_smode<LID, SMODE_F64>(flags, p, s);
-    case SMODE_F32: return stencil_detail::launch_smode<LID, SMODE_F32>(flags, p, s);
-    case SMODE_RESID: return stencil_detail::launch_smode<LID, SMODE_RESID>(flags, p, s);
+    case SMODE_F64: return launch_stencil_mode_tu<LID, SMODE_F64>(flags, p, s);
+    case SMODE_F32: return launch_stencil_mode_tu<LID, SMODE_F32>(flags, p, s);
+    case SMODE_RESID: return launch_stencil_mode_tu<LID, SMODE_RESID>(flags, p, s);
   }
   return hipErrorInvalidValue;
 }

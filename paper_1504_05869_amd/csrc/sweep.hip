@@ -153,9 +153,16 @@ hipError_t launch_stencil(int lattice, int smode, int flags, const StencilParams
   return hipErrorInvalidValue;
 }
 
-unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz) {
-  const StencilShape sh = stencil_shape(velocity_table(lattice).dim);
+unsigned stencil_blocks(int lattice, unsigned nx, unsigned ny, unsigned nz, int tile) {
+  const StencilShape sh = stencil_tile_shape(velocity_table(lattice).dim, tile);
   return ((nx + sh.tx - 1) / sh.tx) * ((ny + sh.ty - 1) / sh.ty) * ((nz + sh.tz - 1) / sh.tz);
+}
+
+unsigned stencil_blocks_max(int lattice, unsigned nx, unsigned ny, unsigned nz) {
+  unsigned m = 0;
+  for (int t = 0; t < stencil_tiles(velocity_table(lattice).dim); ++t)
+    m = std::max(m, stencil_blocks(lattice, nx, ny, nz, t));
+  return m;
 }
 
 hipError_t launch_finish(const double *partials, unsigned nblocks, double *out, hipStream_t s) {

@@ -53,6 +53,38 @@ def test_stencil_form_equals_population_sweep(lattice):
     assert rel_l2(fa, fb) <= 1e-13
 
 
+@pytest.mark.parametrize("lattice", ["D3Q111", "D3Q107"])
+def test_stencil3_every_tile_and_block_order_same_bits(lattice):
+    """Every 3D tile variant and block order the runtime chooses between gives
+    bitwise the same sweeps (each output cell accumulates in the same order),
+    on a ragged grid, FP64 and FP32, and matches the oracle."""
+    import os
+    shape = (37, 45, 150)
+    s = _src(shape, 11)
+    for precision, bar in (("f64", 1e-13), ("f32", 5e-6)):
+        out = []
+        for tile in range(6):
+            for remap in (0, 4, 16):
+                os.environ["LKP_STENCIL_TILE"] = str(tile)
+                os.environ["LKP_STENCIL_REMAP"] = str(remap)
+                try:
+                    with lkp.Problem(s, lattice, 5, tau_lb=1.0, precision=precision) as p:
+                        info = p.info()
+                        assert (info["stencil_tile"], info["stencil_remap"]) == (tile, remap)
+                        rep = p.solve(tol_rel_l2=1e-300, max_sweeps=6, check_every=3,
+                                      raise_on_error=False)
+                        out.append((p.phi_host(), rep["l2_change"], rep["phi_l2"]))
+                finally:
+                    os.environ.pop("LKP_STENCIL_TILE", None)
+                    os.environ.pop("LKP_STENCIL_REMAP", None)
+        for phi, l2c, l2 in out[1:]:
+            assert np.array_equal(phi, out[0][0]) and l2c == out[0][1] and l2 == out[0][2]
+        ref, _ = SW.run(SW.Problem(lattice, 5, 1.0, s), 6)
+        err = rel_l2(out[0][0], ref)
+        say(lattice, precision, "18 tile/order variants bitwise equal; vs oracle", err)
+        assert err <= bar
+
+
 @pytest.mark.parametrize("shape", [(37, 40, 150), (32, 16, 64), (5, 33, 70)])
 @pytest.mark.parametrize("precision,bar", [("f64", 1e-13), ("f32", 5e-6)])
 def test_stencil3_multi_tile(shape, precision, bar):
