@@ -57,7 +57,8 @@ def test_stencil_form_equals_population_sweep(lattice):
 def test_stencil3_every_tile_and_block_order_same_bits(lattice):
     """Every 3D tile variant and block order the runtime chooses between gives
     bitwise the same sweeps (each output cell accumulates in the same order),
-    on a ragged grid, FP64 and FP32, and matches the oracle."""
+    on a ragged grid, FP64 and FP32, and matches the oracle.  The reduced
+    norms group their partial sums by block, so they agree to rounding."""
     import os
     shape = (37, 45, 150)
     s = _src(shape, 11)
@@ -78,7 +79,8 @@ def test_stencil3_every_tile_and_block_order_same_bits(lattice):
                     os.environ.pop("LKP_STENCIL_TILE", None)
                     os.environ.pop("LKP_STENCIL_REMAP", None)
         for phi, l2c, l2 in out[1:]:
-            assert np.array_equal(phi, out[0][0]) and l2c == out[0][1] and l2 == out[0][2]
+            assert np.array_equal(phi, out[0][0])
+            assert abs(l2c - out[0][1]) <= 1e-14 * out[0][1] and abs(l2 - out[0][2]) <= 1e-14 * out[0][2]
         ref, _ = SW.run(SW.Problem(lattice, 5, 1.0, s), 6)
         err = rel_l2(out[0][0], ref)
         say(lattice, precision, "18 tile/order variants bitwise equal; vs oracle", err)
