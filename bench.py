@@ -357,57 +357,76 @@ def say(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def extras_rates(lkp, torch, W) -> list:
-    """Per-sweep rates of the other sets, orders, precisions and forms."""
-    s = W.poisson_source("blobs2d", (1024, 1024), seed=12345)
+def extras_rates(lkp, torch, W, only: str = "") -> list:
+    """Per-sweep rates of the other sets, orders, precisions and forms (with
+    `only`: just the lines whose form contains that text)."""
     kn = 0.1
-    extras = []
+    cache = {}
+
+    def src(kind, shape, seed):
+        key = (kind, shape, seed)
+        if key not in cache:
+            cache.clear()
+            cache[key] = W.poisson_source(kind, shape, seed=seed)
+        return cache[key]
+
+    s2 = lambda: src("blobs2d", (1024, 1024), 12345)
+    s3 = lambda: src("blobs3d", (256, 256, 256), 12345)
+    jobs = []   # (form, thunk)
     for N, lat in ORDERS.items():
         for prec in ("f64", "f32"):
-            extras.append(dict(sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200),
-                               grid="1024^2"))
+            jobs.append(("population sweep", lambda N=N, lat=lat, prec=prec: dict(
+                sweep_rate(lkp, torch, s2(), lat, N, prec, knudsen=kn, sweeps=200), grid="1024^2")))
     # generated minimal sets (square-symmetric shells) for the same orders
     for N, lat in ((5, "D2Q37"), (7, "D2Q77")):
         for prec in ("f64", "f32"):
-            extras.append(dict(sweep_rate(lkp, torch, s, lat, N, prec, knudsen=kn, sweeps=200),
-                               form="generated set", grid="1024^2"))
+            jobs.append(("generated set", lambda N=N, lat=lat, prec=prec: dict(
+                sweep_rate(lkp, torch, s2(), lat, N, prec, knudsen=kn, sweeps=200),
+                form="generated set", grid="1024^2")))
     # in place (one population buffer): every sweep pair gathers/scatters once
     for prec in ("f64", "f32"):
-        extras.append(dict(sweep_rate(lkp, torch, s, "D2Q81", 5, prec, knudsen=kn, sweeps=200,
-                                      in_place=True), grid="1024^2"))
-    s3 = W.poisson_source("blobs3d", (256, 256, 256), seed=12345)
+        jobs.append(("population sweep, in place", lambda prec=prec: dict(
+            sweep_rate(lkp, torch, s2(), "D2Q81", 5, prec, knudsen=kn, sweeps=200, in_place=True),
+            grid="1024^2")))
     for prec in ("f32", "f64"):
-        extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
-                                      sweeps=40, population_sweep=True), grid="256^3"))
+        jobs.append(("population sweep", lambda prec=prec: dict(
+            sweep_rate(lkp, torch, s3(), "D3Q111", 5, prec, tau_lb=1.0, sweeps=40,
+                       population_sweep=True), grid="256^3")))
         # the generated 3D set with 107 velocities, same problem
-        extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q107", 5, prec, tau_lb=1.0,
-                                      sweeps=40, population_sweep=True), grid="256^3",
-                           form="generated set"))
-        extras.append(dict(sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0,
-                                      sweeps=40, population_sweep=True, in_place=True),
-                           grid="256^3"))
+        jobs.append(("generated set", lambda prec=prec: dict(
+            sweep_rate(lkp, torch, s3(), "D3Q107", 5, prec, tau_lb=1.0, sweeps=40,
+                       population_sweep=True), grid="256^3", form="generated set")))
+        jobs.append(("population sweep, in place", lambda prec=prec: dict(
+            sweep_rate(lkp, torch, s3(), "D3Q111", 5, prec, tau_lb=1.0, sweeps=40,
+                       population_sweep=True, in_place=True), grid="256^3")))
+
     # BF16 deviation storage (ablation): plain deviation sweeps; bytes = n_i
     # read + write (BF16), Phi read + write and S (FP32)
-    r = sweep_rate(lkp, torch, s, "D2Q81", 5, "bf16dev_ir", knudsen=kn, sweeps=200)
-    bpc_dev = 4 * r_q(lkp, "D2Q81") + 12
-    r.update(form="BF16 deviation storage", grid="1024^2",
-             gbs=s.size * bpc_dev / (r["ms_per_sweep"] * 1e-3) / 1e9)
-    r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
-    extras.append(r)
+    def bf16dev():
+        r = sweep_rate(lkp, torch, s2(), "D2Q81", 5, "bf16dev_ir", knudsen=kn, sweeps=200)
+        bpc_dev = 4 * r_q(lkp, "D2Q81") + 12
+        r.update(form="BF16 deviation storage", grid="1024^2",
+                 gbs=s2().size * bpc_dev / (r["ms_per_sweep"] * 1e-3) / 1e9)
+        r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
+        return r
+    jobs.append(("BF16 deviation storage", bf16dev))
     # D3Q107 on the headline problem (512^3, Kn = 0.3, FP64, two buffers): the
     # same sweep with 4 fewer velocities (the headline line is D3Q111)
-    s5 = W.poisson_source(C5["kind"], C5["shape"], seed=C5["seed"])
-    extras.append(dict(sweep_rate(lkp, torch, s5, "D3Q107", 5, "f64", knudsen=C5["knudsen"],
-                                  sweeps=20), grid="512^3", form="generated set"))
-    del s5
+    jobs.append(("generated set", lambda: dict(
+        sweep_rate(lkp, torch, src(C5["kind"], C5["shape"], C5["seed"]), "D3Q107", 5, "f64",
+                   knudsen=C5["knudsen"], sweeps=20), grid="512^3", form="generated set")))
+
     # tau_lb = 1: the stencil form (state Phi, 3 values moved per cell)
-    for prec in ("f32", "f64"):
-        r = sweep_rate(lkp, torch, s3, "D3Q111", 5, prec, tau_lb=1.0, sweeps=200)
+    def stencil(prec):
+        r = sweep_rate(lkp, torch, s3(), "D3Q111", 5, prec, tau_lb=1.0, sweeps=200)
         b = 4 if prec == "f32" else 8
         r.update(form="stencil (tau_lb=1)", grid="256^3",
-                 gbs=s3.size * 3 * b / (r["ms_per_sweep"] * 1e-3) / 1e9)
+                 gbs=s3().size * 3 * b / (r["ms_per_sweep"] * 1e-3) / 1e9)
         r["frac_hbm"] = r["gbs"] / HBM_PEAK_GBS
-        extras.append(r)
+        return r
+    for prec in ("f32", "f64"):
+        jobs.append(("stencil (tau_lb=1)", lambda prec=prec: stencil(prec)))
+    extras = [thunk() for form, thunk in jobs if only in form]
     return [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in e.items()} for e in extras]
 
 
@@ -521,6 +540,8 @@ def main():
     ap.add_argument("--rates-only", action="store_true",
                     help="only the per-sweep rates of the other sets, precisions and forms "
                          "(counter runs of those kernels)")
+    ap.add_argument("--only", default="",
+                    help="with --rates-only: keep the rate lines whose form contains this text")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -542,7 +563,7 @@ def main():
         print(json.dumps({"configs": configs_matrix(lkp, torch, W)}), flush=True)
         return
     if args.rates_only:
-        print(json.dumps({"sweeps": extras_rates(lkp, torch, W)}), flush=True)
+        print(json.dumps({"sweeps": extras_rates(lkp, torch, W, args.only)}), flush=True)
         return
     if args.calibrate_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB

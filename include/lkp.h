@@ -233,9 +233,13 @@ typedef struct lkp_handle_info {
   int32_t lattice, order, dim, Q, precision, velocity_groups;
   int32_t scalar_stencil;   /* 1: omega = 1 stencil form (state is Phi) */
   int32_t in_place;         /* 1: one population buffer swept in place (LKP_FLAG_IN_PLACE) */
-  int32_t stencil_tile;     /* 3D stencil form: tile variant chosen by timing (output tile
-                               64 x 4CY x BZ with (CY, BZ) = (2,32) (2,16) (2,8) (4,16) (4,8)
-                               (1,16) for 0..5); every variant gives the same bits; else -1 */
+  int32_t stencil_tile;     /* 3D stencil form: tile variant chosen by timing, output tile
+                               64 x 4CY x BZ: 0..5 velocity by velocity with (CY, BZ) =
+                               (2,32) (2,16) (2,8) (4,16) (4,8) (1,16); 6..9 separable (sums
+                               over +-x, then +-y offsets, then one weight per offset
+                               magnitude) with (2,32) (2,16) (1,16) (4,16).  The variants of
+                               one family give the same bits, the families agree to rounding;
+                               else -1 */
   int32_t stencil_remap;    /* 3D stencil form: 0 hardware block order, R > 0 runs of R
                                blocks per XCD; else -1 */
   int64_t n[3];

@@ -125,9 +125,15 @@ struct StencilParams {
 struct StencilShape {
   unsigned tx, ty, tz;
 };
-constexpr int kStencilTiles3 = 6;
-constexpr int kStencilCY[kStencilTiles3] = {2, 2, 2, 4, 4, 1};
-constexpr int kStencilBZ[kStencilTiles3] = {32, 16, 8, 16, 8, 16};
+// Variants 0..5 take the stencil velocity by velocity; 6..9 ("separable")
+// use the symmetry of the shell sets: sums over +-x offsets first, then over
+// +-y, then weights per (x, y, z) offset magnitude, which is less than half
+// the arithmetic.  The two families round differently.
+constexpr int kStencilTiles3 = 10;
+constexpr int kStencilCY[kStencilTiles3] = {2, 2, 2, 4, 4, 1, 2, 2, 1, 4};
+constexpr int kStencilBZ[kStencilTiles3] = {32, 16, 8, 16, 8, 16, 32, 16, 16, 16};
+constexpr bool kStencilSep[kStencilTiles3] = {false, false, false, false, false, false,
+                                              true, true, true, true};
 constexpr StencilShape stencil_tile_shape(int dim, int tile) {
   return dim == 1 ? StencilShape{256, 1, 1}
                   : (dim == 2 ? StencilShape{64, 16, 1}

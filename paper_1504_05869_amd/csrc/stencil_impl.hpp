@@ -227,9 +227,45 @@ struct Plan3 {
   static constexpr Table t = make();
 };
 
-template <int LID, int SM, int FLAGS, int CY, int BZ>
+// Separable form for sets made of whole shells (every sign change of a
+// velocity is in the set, with the same weight): the sum over a shell is a sum
+// over its distinct component permutations (a, b, c) >= 0 of
+//   S_c^z S_b^y S_a^x Phi,   S_d f(x) = f(x + d) + f(x - d) (d > 0), S_0 f = f.
+// orb[a][b][c] is the weight (orbit) index of the permutation, or -1.
+template <int LID>
+struct SepPlan3 {
+  using L = Lattice<LID>;
+  static constexpr int AX = L::VMX, AY = L::VMY, AZ = L::VMZ;
+  struct Table {
+    signed char orb[AX + 1][AY + 1][AZ + 1];
+    bool pair[AX + 1][AY + 1];
+    bool closed;  // every sign change of every velocity is in the set, same orbit
+  };
+  static constexpr Table make() {
+    Table t{};
+    t.closed = true;
+    for (int a = 0; a <= AX; ++a)
+      for (int b = 0; b <= AY; ++b) {
+        t.pair[a][b] = false;
+        for (int c = 0; c <= AZ; ++c) {
+          const int i = L::vel(a, b, c);
+          t.orb[a][b][c] = (signed char)(i >= 0 ? L::orbit(i) : -1);
+          if (i >= 0) t.pair[a][b] = true;
+          for (int sg = 1; sg < 8; ++sg) {
+            const int j = L::vel((sg & 1) ? -a : a, (sg & 2) ? -b : b, (sg & 4) ? -c : c);
+            if ((i >= 0) != (j >= 0) || (i >= 0 && L::orbit(i) != L::orbit(j))) t.closed = false;
+          }
+        }
+      }
+    return t;
+  }
+  static constexpr Table t = make();
+};
+
+template <int LID, int SM, int FLAGS, int CY, int BZ, bool SEP>
 __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
   using Plan = Plan3<LID, CY>;
+  using SP = SepPlan3<LID>;
   using L = Lattice<LID>;
   using MT = SModeTraits<SM>;
   using TIN = typename MT::TIN;
@@ -243,7 +279,11 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
   constexpr int NST = (NL + 255) / 256;  // staging loads per thread and plane
   constexpr int NSTEPS = BZ + 2 * VMZ;   // input planes per block
   constexpr bool CENTRE = MT::RESID || (FLAGS & FLAG_REDUCE) != 0;
+  static_assert(!SEP || SP::t.closed, "the separable form needs a set of whole shells");
   __shared__ TIN tile[2][NL];
+  // separable form: S_a^x Phi of the current input plane, a = 1..VMX, on all
+  // LY rows of the tile (no x halo)
+  __shared__ TC xs[SEP ? VMX : 1][SEP ? TX * LY : 1];
 
   const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
   // one linear grid; p.remap > 0 deals runs of p.remap consecutive blocks
@@ -303,12 +343,79 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
 #pragma unroll
           for (int k = 0; k < CY; ++k) cen[cs][k] = (TC)t[(ly0 + k + VMY) * LX + tx + VMX];
         }
+        if constexpr (SEP) {
+          // x sums of this plane for every tile row (rows dealt over the 4
+          // row groups), then the block meets before the y sums read them
+          const int rg = (int)(threadIdx.x / TX);
+#pragma unroll
+          for (int r0 = 0; r0 < LY; r0 += RY) {
+            const int r = r0 + rg;
+            if (r0 + RY <= LY || r < LY) {
+              const TIN *row = t + r * LX + tx + VMX;
+              static_for<1, VMX + 1>([&](auto A) __attribute__((always_inline)) {
+                constexpr int a = (int)A;
+                xs[a - 1][r * TX + tx] = (TC)row[a] + (TC)row[-a];
+              });
+            }
+          }
+          __syncthreads();
+          constexpr int NR = CY + 2 * VMY;
+          static_for<0, VMX + 1>([&](auto A) __attribute__((always_inline)) {
+            constexpr int a = (int)A;
+            TC col[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+              col[r] = a == 0 ? (TC)t[(ly0 + r) * LX + tx + VMX] : xs[a == 0 ? 0 : a - 1][(ly0 + r) * TX + tx];
+            static_for<0, VMY + 1>([&](auto B) __attribute__((always_inline)) {
+              constexpr int b = (int)B;
+              if constexpr (SP::t.pair[a][b]) {
+#pragma unroll
+                for (int k = 0; k < CY; ++k) {
+                  const TC y = b == 0 ? col[k + VMY] : col[k + VMY + b] + col[k + VMY - b];
+                  static_for<0, VMZ + 1>([&](auto Cz) __attribute__((always_inline)) {
+                    constexpr int c = (int)Cz;
+                    constexpr int o = SP::t.orb[a][b][c];
+                    if constexpr (o >= 0) {
+                      TC w;
+                      if constexpr (sizeof(TC) == 8) w = (TC)p.coef.d[o];
+                      else w = (TC)p.coef.f[o];
+                      // input plane step feeds outputs m = step - VMZ + vz, vz = +-c
+                      constexpr int sp = ((ph - VMZ + c) % NZR + NZR) % NZR;
+                      acc[sp][k] = FmaT<SM>::f(w, y, acc[sp][k]);
+                      if constexpr (c > 0) {
+                        constexpr int sm = ((ph - VMZ - c) % NZR + NZR) % NZR;
+                        acc[sm][k] = FmaT<SM>::f(w, y, acc[sm][k]);
+                      }
+                    }
+                  });
+                }
+              }
+            });
+#pragma unroll
+            for (int j = 0; j < NZR; ++j)
+#pragma unroll
+              for (int k = 0; k < CY; ++k) asm volatile("" : "+v"(acc[j][k]) : : "memory");
+          });
+        } else {
+        // Columns of staged values (one x-offset each) are read one column
+        // ahead: the LDS reads of column ix + 1 are in flight while the
+        // multiply-adds of column ix run, so the LDS and the FP pipes overlap.
+        constexpr int NR = CY + 2 * VMY;
+        TC col[2][NR];
+        auto read_col = [&](auto IXc) __attribute__((always_inline)) {
+          constexpr int ix = (int)IXc;
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            if (Plan::t.used[ix][r]) col[ix & 1][r] = (TC)t[(ly0 + r) * LX + tx + 2 * VMX - ix];  // vx = ix - VMX
+        };
+        read_col(std::integral_constant<int, 0>{});
         static_for<0, 2 * VMX + 1>([&](auto IX) __attribute__((always_inline)) {
           constexpr int ix = (int)IX;
+          if constexpr (ix + 1 < 2 * VMX + 1) read_col(std::integral_constant<int, ix + 1>{});
 #pragma unroll
-          for (int r = 0; r < CY + 2 * VMY; ++r) {
+          for (int r = 0; r < NR; ++r) {
             if (Plan::t.used[ix][r]) {
-              const TC val = (TC)t[(ly0 + r) * LX + tx + 2 * VMX - ix];  // vx = ix - VMX
+              const TC val = col[ix & 1][r];
 #pragma unroll
               for (int k = 0; k < CY; ++k)
 #pragma unroll
@@ -324,12 +431,14 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
                 }
             }
           }
-          // compiler-only fence: keeps one column of staged values live at a time
+          // compiler-only fence: at most two columns of staged values live,
+          // and the reads of the column after next stay below this point
 #pragma unroll
           for (int j = 0; j < NZR; ++j)
 #pragma unroll
             for (int k = 0; k < CY; ++k) asm volatile("" : "+v"(acc[j][k]) : : "memory");
         });
+        }
         // output plane m = step - 2 VMZ is complete
         constexpr int fs = (ph + 1) % NZR;
         const int m = step - 2 * VMZ;
@@ -381,23 +490,28 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
 template <int LID, int SM, int TILE>
 hipError_t launch_tile3(int flags, StencilParams p, hipStream_t s) {
   constexpr int CY = kStencilCY[TILE], BZ = kStencilBZ[TILE];
-  constexpr StencilShape sh = stencil_tile_shape(3, TILE);
-  p.gbx = (p.nx + sh.tx - 1) / sh.tx;
-  p.gby = (p.ny + sh.ty - 1) / sh.ty;
-  const unsigned gbz = (p.nz + sh.tz - 1) / sh.tz;
-  const dim3 grid(p.gbx * p.gby * gbz);
-  if (flags & FLAG_REDUCE)
-    hipLaunchKernelGGL((k_stencil3<LID, SM, FLAG_REDUCE, CY, BZ>), grid, dim3(256), 0, s, p);
-  else
-    hipLaunchKernelGGL((k_stencil3<LID, SM, 0, CY, BZ>), grid, dim3(256), 0, s, p);
-  return hipGetLastError();
+  constexpr bool SEP = kStencilSep[TILE];
+  if constexpr (SEP && !SepPlan3<LID>::t.closed) {
+    return hipErrorInvalidValue;  // not a set of whole shells
+  } else {
+    constexpr StencilShape sh = stencil_tile_shape(3, TILE);
+    p.gbx = (p.nx + sh.tx - 1) / sh.tx;
+    p.gby = (p.ny + sh.ty - 1) / sh.ty;
+    const unsigned gbz = (p.nz + sh.tz - 1) / sh.tz;
+    const dim3 grid(p.gbx * p.gby * gbz);
+    if (flags & FLAG_REDUCE)
+      hipLaunchKernelGGL((k_stencil3<LID, SM, FLAG_REDUCE, CY, BZ, SEP>), grid, dim3(256), 0, s, p);
+    else
+      hipLaunchKernelGGL((k_stencil3<LID, SM, 0, CY, BZ, SEP>), grid, dim3(256), 0, s, p);
+    return hipGetLastError();
+  }
 }
 
 template <int LID, int SM>
 hipError_t launch_smode(int flags, const StencilParams &p, hipStream_t s) {
   constexpr int DIM = Lattice<LID>::DIM;
   if constexpr (DIM == 3) {
-    static_assert(kStencilTiles3 == 6, "one case per tile variant");
+    static_assert(kStencilTiles3 == 10, "one case per tile variant");
     switch (p.tile) {
       case 0: return launch_tile3<LID, SM, 0>(flags, p, s);
       case 1: return launch_tile3<LID, SM, 1>(flags, p, s);
@@ -405,6 +519,10 @@ hipError_t launch_smode(int flags, const StencilParams &p, hipStream_t s) {
       case 3: return launch_tile3<LID, SM, 3>(flags, p, s);
       case 4: return launch_tile3<LID, SM, 4>(flags, p, s);
       case 5: return launch_tile3<LID, SM, 5>(flags, p, s);
+      case 6: return launch_tile3<LID, SM, 6>(flags, p, s);
+      case 7: return launch_tile3<LID, SM, 7>(flags, p, s);
+      case 8: return launch_tile3<LID, SM, 8>(flags, p, s);
+      case 9: return launch_tile3<LID, SM, 9>(flags, p, s);
     }
     return hipErrorInvalidValue;
   } else {
