@@ -345,7 +345,8 @@ def serving_run(n_requests: int, rate: float, full_sizes: bool = False) -> dict:
                       f"{sizes}, Kn~U(0.05,0.5), Gaussian blobs, retire at estimated rel-L2 1e-6",
             "hbm_budget_bytes": budget,
             "batched_f32_ir": {k: summ[k] for k in keys}
-                              | {k: summ[k] for k in ("ticks", "graph_captures", "graph_replays")
+                              | {k: summ[k] for k in ("ticks", "graph_captures", "graph_replays",
+                                                      "graph_splits")
                                  if k in summ}
                               | {"true_rel_l2": err_stats(errs["batched"])},
             "one_at_a_time_f64": {k: bsum[k] for k in keys}
@@ -540,6 +541,9 @@ def main():
     ap.add_argument("--rates-only", action="store_true",
                     help="only the per-sweep rates of the other sets, precisions and forms "
                          "(counter runs of those kernels)")
+    ap.add_argument("--skip-headline", action="store_true",
+                    help="leave out the 512^3 headline (profiling the other parts only; the "
+                         "printed line then carries no headline fields)")
     ap.add_argument("--only", default="",
                     help="with --rates-only: keep the rate lines whose form contains this text")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -573,8 +577,11 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    out = headline(lkp, torch, args)
-    say(f"headline: {out['value']} GLUPS, sweep {out['roofline']['achieved']} GB/s")
+    if args.skip_headline:
+        out = {}
+    else:
+        out = headline(lkp, torch, args)
+        say(f"headline: {out['value']} GLUPS, sweep {out['roofline']['achieved']} GB/s")
     if not args.no_extras and not args.serving_only:
         out["sweeps"] = extras_rates(lkp, torch, W)
         say("extras: rates done")

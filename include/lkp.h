@@ -362,6 +362,15 @@ lkp_status lkp_group_remove(lkp_group *g, lkp_handle *h);
 lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, int32_t capacity,
                           int32_t *count);
 
+/* The group's velocity-group split P of its batched sweeps.  At the first step
+ * with enough work to time (2^18 cells over the running members) the group
+ * times every built split of its batched sweep (F32_IR: the correction
+ * sweep) on its members' own buffers (the state is unchanged) and keeps the
+ * fastest, cached for the class (set, precision) in the process; every split
+ * gives the same bits, so answers are the same alone and in any mix.
+ * LKP_SPLIT forces a split, LKP_AUTOTUNE=0 keeps the default. */
+lkp_status lkp_group_split(const lkp_group *g, int32_t *velocity_groups);
+
 /* Counters of the group's captured steps: graphs captured and steps replayed
  * from a graph since creation (either pointer may be NULL). */
 lkp_status lkp_group_graph_stats(const lkp_group *g, int64_t *captures, int64_t *replays);

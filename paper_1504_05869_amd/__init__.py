@@ -270,6 +270,13 @@ class Group:
                         "max_change": r.max_change, "phi_l2": r.phi_l2})
         return out
 
+    def split(self) -> int:
+        """Velocity-group split of the group's batched sweeps (chosen at its
+        first step with enough work)."""
+        P = ctypes.c_int32()
+        check(self._lib.lkp_group_split(self._g, ctypes.byref(P)), "lkp_group_split")
+        return P.value
+
     def graph_stats(self) -> dict:
         """Graphs captured and steps replayed from a graph so far."""
         c, r = ctypes.c_int64(), ctypes.c_int64()

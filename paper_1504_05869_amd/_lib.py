@@ -22,7 +22,8 @@ EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_solve", "lkp
            "lkp_lattice_info", "lkp_get_info", "lkp_get_coefficients", "lkp_set_equilibrium",
            "lkp_sync", "lkp_last_error",
            "lkp_group_create", "lkp_group_add", "lkp_group_remove", "lkp_group_step",
-           "lkp_group_destroy", "lkp_group_graph_stats"]
+           "lkp_group_destroy", "lkp_group_graph_stats", "lkp_group_split",
+           "lkp_residual_noalloc"]
 MEMBER_STATES = {0: "running", 1: "converged", 2: "failed"}
 FLAG_POPULATION_SWEEP = 1
 FLAG_IN_PLACE = 2
@@ -123,6 +124,7 @@ def load() -> ctypes.CDLL:
                                           P(ctypes.c_int32)]),
         "lkp_group_destroy": (ctypes.c_int, [H]),
         "lkp_group_graph_stats": (ctypes.c_int, [H, P(ctypes.c_int64), P(ctypes.c_int64)]),
+        "lkp_group_split": (ctypes.c_int, [H, P(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "kernels.hpp"
@@ -19,6 +21,7 @@ using namespace lkp::rt;
 struct lkp_group {
   int lattice = 0, order = 0, precision = 0, Q = 0;
   int P = 1;
+  bool tuned = false;   // P chosen (by timing, a forced split, or the class cache)
   hipStream_t stream = nullptr;
   std::vector<lkp_handle *> members;
   double *norms_dev = nullptr;   // NUM_NORMS per member slot
@@ -147,6 +150,7 @@ lkp_status launch_batched(lkp_group *g, int mode, int flags, const std::vector<S
     case 169: return launch_slots<169>(g, mode, flags, slots, out);
     case 37: return launch_slots<37>(g, mode, flags, slots, out);
     case 77: return launch_slots<77>(g, mode, flags, slots, out);
+    case 107: return launch_slots<107>(g, mode, flags, slots, out);
   }
   return fail(LKP_ERR_UNSUPPORTED, "no batched sweep for Q = %d", g->Q);
 }
@@ -367,6 +371,82 @@ lkp_status step_ir(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
   return LKP_OK;
 }
 
+// Process-wide choice of the batched split per class (set, mode): every
+// split gives the same bits (the moment is summed in one fixed order), so
+// the choice only moves the time, and a problem's answer stays the same
+// alone and in any mix.
+std::mutex g_group_mu;
+std::map<long, int> g_group_split;
+
+// Time each built split of the group's batched sweep on the members' own
+// buffers (a few sweeps from the current state into the idle buffer: the
+// state is unchanged) and keep the fastest for the class.
+lkp_status tune_group(lkp_group *g, const std::vector<lkp_handle *> &run) {
+  g->tuned = true;
+  if (std::getenv("LKP_SPLIT")) return LKP_OK;
+  const char *off = std::getenv("LKP_AUTOTUNE");
+  if (off && std::atoi(off) == 0) return LKP_OK;
+  const long key = (long)g->lattice * 16 + g->mode();
+  {
+    std::lock_guard<std::mutex> lk(g_group_mu);
+    auto it = g_group_split.find(key);
+    if (it != g_group_split.end()) {
+      g->P = it->second;
+      return LKP_OK;
+    }
+  }
+  int64_t cells = 0;
+  for (const lkp_handle *h : run) cells += h->ncells;
+  if (cells < (int64_t(1) << 18)) return LKP_OK;  // too little work to time: keep the default
+  // refinement groups: the correction sweep (FP32 d -> the idle correction
+  // buffer with the residual source; contents do not matter for timing) at
+  // splits built for the first solves' FP32 sweep as well
+  const bool ir = g->precision == LKP_F32_IR;
+  std::vector<Slot> slots(run.size());
+  for (size_t k = 0; k < run.size(); ++k) {
+    lkp_handle *h = run[k];
+    slots[k] = ir ? Slot{h, h->d32[0], h->d32[1], h->r32, nullptr, nullptr}
+                  : Slot{h, h->f[h->cur], h->f[1 - h->cur], h->S, nullptr, nullptr};
+  }
+  hipEvent_t e0, e1;
+  LKP_HIP_TRY(hipEventCreate(&e0));
+  LKP_HIP_TRY(hipEventCreate(&e1));
+  const int saved = g->P;
+  float best = 1e30f;
+  int bestP = saved;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int P : {1, 2, 4}) {
+      if (!sweep_variant_available(g->lattice, g->mode(), P)) continue;
+      if (ir && !sweep_variant_available(g->lattice, MODE_F32, P)) continue;
+      g->P = P;
+      if (lkp_status st = launch_batched(g, g->mode(), 0, slots, Sink{g->stream, nullptr})) {
+        g->P = saved;
+        return st;
+      }
+      LKP_HIP_TRY(hipEventRecord(e0, g->stream));
+      for (int r = 0; r < 3; ++r)
+        if (lkp_status st = launch_batched(g, g->mode(), 0, slots, Sink{g->stream, nullptr})) {
+          g->P = saved;
+          return st;
+        }
+      LKP_HIP_TRY(hipEventRecord(e1, g->stream));
+      LKP_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      LKP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (pass == 1 && ms < best) {   // the first pass warms every variant
+        best = ms;
+        bestP = P;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g->P = bestP;
+  for (lkp_handle *h : g->members) h->split = bestP;
+  std::lock_guard<std::mutex> lk(g_group_mu);
+  g_group_split[key] = bestP;
+  return LKP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -392,6 +472,7 @@ lkp_status lkp_group_create(int32_t lattice, int32_t order, int32_t precision, v
   if (const char *env = std::getenv("LKP_SPLIT")) {
     const int P = std::atoi(env);
     if (sweep_variant_available(lattice, g->mode(), P)) g->P = P;
+    g->tuned = true;
   }
   if (const char *env = std::getenv("LKP_GROUP_GRAPH")) g->use_graph = std::atoi(env) != 0;
   *out = g;
@@ -451,6 +532,8 @@ lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, 
   std::vector<lkp_handle *> run;
   for (lkp_handle *h : g->members)
     if (h->gstate == LKP_MEMBER_RUNNING) run.push_back(h);
+  if (!run.empty() && !g->tuned)
+    if (lkp_status st = tune_group(g, run)) return st;
   if (!run.empty()) {
     lkp_status st = g->precision == LKP_F32_IR ? step_ir(g, sweeps, run) : step_plain(g, sweeps, run);
     if (st != LKP_OK) return st;
@@ -473,6 +556,12 @@ lkp_status lkp_group_step(lkp_group *g, int32_t sweeps, lkp_member_report *out, 
   }
   if (count) *count = n;
   clear_error();
+  return LKP_OK;
+}
+
+lkp_status lkp_group_split(const lkp_group *g, int32_t *velocity_groups) {
+  if (!g || !velocity_groups) return fail(LKP_ERR_ARG, "lkp_group_split: null argument");
+  *velocity_groups = g->P;
   return LKP_OK;
 }
 

@@ -160,9 +160,11 @@ unsigned stencil_blocks_max(int lattice, unsigned nx, unsigned ny, unsigned nz);
 // P waves share one 64-cell column and each holds Q/P populations).
 inline unsigned cells_per_block(int P) { return 256u / (unsigned)P; }
 
-// The one split of the refinement's correction sweep (MODE_INNER), measured
+// Default split of the refinement's correction sweep (MODE_INNER), measured
 // fastest on MI355X: 1 up to 81 velocities, 2 for 107 and 111, 4 for 169.  FP32 first
-// solves of a refinement use the same split, so it is built for MODE_F32 too.
+// solves of a refinement use the same split as the corrections, so every split
+// built for MODE_INNER is built for MODE_F32 too; the runtime times the
+// candidates.
 constexpr int inner_split(int q) { return q >= 169 ? 4 : (q >= 100 ? 2 : 1); }
 
 // Velocity-group splits compiled per (lattice, mode): small sets P = 1; for
@@ -172,12 +174,11 @@ constexpr bool sweep_variant_built(int lattice, int mode, int P) {
   const bool wide = (mode == MODE_F64 || mode == MODE_RESID);
   if (q <= 25) return P == 1;
   if (mode == MODE_RESID) return P == (q >= 169 ? 4 : 2);
-  if (mode == MODE_INNER) return P == inner_split(q);
+  if (mode == MODE_INNER) return q >= 169 ? (P == 2 || P == 4) : (P == 1 || P == 2);
   if (wide) {
     if (q <= 81) return P == 1 || P == 2;
     return P == 2 || P == 4;
   }
-  if (q <= 81) return P == 1;
   if (q >= 169) return P == 1 || P == 2 || P == 4;
   return P == 1 || P == 2;
 }

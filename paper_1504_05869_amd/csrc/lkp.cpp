@@ -373,15 +373,19 @@ lkp_status tune_split(lkp_handle *h) {
   }
   const char *off = std::getenv("LKP_AUTOTUNE");
   // in place, a timing sweep would change the state: no tuning
-  if ((off && std::atoi(off) == 0) || h->ncells < 4096 || h->precision == LKP_F32_IR || h->inplace) {
+  if ((off && std::atoi(off) == 0) || h->ncells < 4096 || h->inplace) {
     h->split = default_split(h->Q, mode);
     return LKP_OK;
   }
+  // refinement: the correction sweep (FP32 d -> the idle correction buffer,
+  // residual source; contents do not matter for timing), at splits built for
+  // the FP32 first solve as well
+  const bool ir = h->precision == LKP_F32_IR;
   auto sweep_once = [&](int P) -> lkp_status {
     SweepParams p = base_params(h);
-    p.fin = h->f[h->cur];
-    p.fout = h->f[1 - h->cur];
-    p.src = h->S;
+    p.fin = ir ? (const void *)h->d32[0] : h->f[h->cur];
+    p.fout = ir ? (void *)h->d32[1] : h->f[1 - h->cur];
+    p.src = ir ? (const void *)h->r32 : h->S;
     set_coefficients(h, mode, &p);
     hipError_t e = launch_sweep(h->lattice, mode, P, 0, p, h->stream);
     if (e != hipSuccess) return fail(LKP_ERR_HIP, "tuning sweep: %s", hipGetErrorString(e));
@@ -395,6 +399,7 @@ lkp_status tune_split(lkp_handle *h) {
   const int saved = h->split;
   for (int P : {1, 2, 4}) {
     if (!sweep_variant_available(h->lattice, mode, P)) continue;
+    if (ir && !sweep_variant_available(h->lattice, MODE_F32, P)) continue;
     h->split = P;
     if (lkp_status st = sweep_once(P)) {
       h->split = saved;

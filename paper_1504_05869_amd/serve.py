@@ -100,11 +100,13 @@ class GpuBackend:
         return p
 
     def graph_stats(self) -> dict:
-        """Captured graphs and graph-replayed steps over every group."""
+        """Captured graphs and graph-replayed steps over every group, and the
+        velocity-group split each class's batched sweeps settled on."""
         tot = {"captures": 0, "replays": 0}
         for g in self.groups.values():
             for k, v in g.graph_stats().items():
                 tot[k] += v
+        tot["splits"] = {f"{lat} N={order}": g.split() for (lat, order), g in self.groups.items()}
         return tot
 
     def tick(self, sweeps: int):

@@ -232,3 +232,41 @@ def test_server_end_to_end_small_stream():
         say(q.shape, q.knudsen, "served err", e_srv, "baseline err", e_base)
         assert e_srv <= 2e-7 and e_base <= 2e-7            # at most 2x the tolerance
     assert summ["peak_hbm_bytes"] <= 2 << 30
+
+
+@pytest.mark.parametrize("precision", ["f32_ir", "f64"])
+def test_group_split_tuned_answers_unchanged(precision):
+    """A group with enough work times its batched splits and keeps one (cached
+    for the class); every split sums the moment in the same order, so each
+    member's answer and sweep count equal its alone solve at a forced split."""
+    specs = [((384, 384), 0.2, 31), ((320, 448), 0.3, 32)]
+    tol = 1e-8
+    os.environ["LKP_SPLIT"] = "2"
+    try:
+        alone = [_alone(s, "D2Q81", 5, precision, 20, tol) for s in specs]
+    finally:
+        os.environ.pop("LKP_SPLIT", None)
+    g = lkp.Group("D2Q81", 5, precision)
+    probs = []
+    try:
+        for shape, kn, seed in specs:
+            p = lkp.Problem(_source(shape, seed), "D2Q81", 5, knudsen=kn, precision=precision)
+            g.add(p, tol_rel_l2=tol)
+            probs.append(p)
+        done = {}
+        for _ in range(100000):
+            for r in g.step(20):
+                if r["state"] == "converged" and r["problem"] not in done:
+                    done[r["problem"]] = (r["problem"].phi_host(), r["sweeps"])
+            if len(done) == len(probs):
+                break
+        P = g.split()
+        say("group split", precision, P)
+        assert P in (1, 2)
+        for p, (phi, sweeps) in zip(probs, alone):
+            assert done[p][1] == sweeps
+            assert np.array_equal(done[p][0], phi)
+    finally:
+        g.close()
+        for p in probs:
+            p.close()
