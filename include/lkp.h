@@ -134,23 +134,40 @@ typedef struct lkp_problem_desc {
                                allow_unstable).  A drifted handle always sweeps populations
                                (also at tau_lb = 1) and cannot join a group.  Zero-initialise
                                the whole description so that older callers get u = 0. */
+  void *workspace;          /* NULL: the handle allocates its device state itself.  Else a
+                               device pointer, 256-byte aligned, to workspace_bytes bytes of
+                               the current device that hold the whole state (populations,
+                               source, Phi buffers, reduction partials): lkp_create carves
+                               them from it and allocates no device memory for the state.
+                               The caller keeps ownership, must not touch the range and must
+                               keep it alive until lkp_destroy returns.  Readbacks that convert
+                               precision (lkp_get_phi / lkp_get_populations / lkp_set_populations
+                               to or from host memory) may still allocate staging buffers. */
+  int64_t workspace_bytes;  /* size of `workspace`; at least lkp_footprint_bytes(d), else
+                               LKP_ERR_ARG; must be 0 when workspace is NULL */
 } lkp_problem_desc;
 
 typedef struct lkp_handle lkp_handle;
 
-/* Create a problem: validates the description, computes the set's weights,
- * c_s^2, phi_i, chi_i (long double, rounded once), scales the source
- * S = s c_s^2 (tau_lb - 1/2), allocates the device state (two population
- * buffers, S, Phi buffers, reduction scratch) and sets f* = 0.
- * Ownership: the handle owns all device memory it allocates; release with
- * lkp_destroy.  Errors: LKP_ERR_ARG, LKP_ERR_LATTICE_ORDER, LKP_ERR_UNSTABLE,
+/* Create a problem (the BGK scheme of Sec. 3 on the set and order of Sec. 4,
+ * source term of Sec. 5): validates the description, computes the set's
+ * weights, c_s^2, phi_i, chi_i (long double, rounded once), scales the source
+ * S = s c_s^2 (tau_lb - 1/2), places the device state (two population
+ * buffers, S, Phi buffers, reduction partials) and sets f* = 0.
+ * Ownership: without a workspace the handle owns all device memory it
+ * allocates; with one, the state lives in the caller's range.  Release with
+ * lkp_destroy.  Errors: LKP_ERR_ARG (also a workspace that is misaligned, too
+ * small, or given without a size), LKP_ERR_LATTICE_ORDER, LKP_ERR_UNSTABLE,
  * LKP_ERR_SOURCE_MEAN, LKP_ERR_OOM, LKP_ERR_HIP; *out is NULL on failure. */
 lkp_status lkp_create(const lkp_problem_desc *d, lkp_handle **out);
 
-/* Release every resource of the handle (NULL is accepted). */
+/* Release every resource of the handle (NULL is accepted): waits for its
+ * stream, frees what it allocated and leaves a caller's workspace alone. */
 lkp_status lkp_destroy(lkp_handle *h);
 
-/* Device bytes lkp_create would allocate for `d` (0 if `d` is invalid). */
+/* Device bytes of the state lkp_create places for `d`: the size of every
+ * buffer, each starting at a 256-byte boundary, i.e. the smallest workspace
+ * that `d` accepts (0 if `d` is invalid; the last error is left as it was). */
 int64_t lkp_footprint_bytes(const lkp_problem_desc *d);
 
 typedef struct lkp_solve_opts {

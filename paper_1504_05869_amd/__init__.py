@@ -58,10 +58,12 @@ def _desc(shape, lattice, order, tau_lb, knudsen, precision, subtract_mean, allo
 
 
 def footprint_bytes(shape, lattice, order, tau_lb=None, knudsen=None, precision="f64",
-                    in_place=False) -> int:
-    """Device bytes a problem of this description allocates (0 if invalid)."""
+                    in_place=False, population_sweep=False) -> int:
+    """Device bytes of the state of a problem of this description, which is
+    also the smallest workspace it accepts (0 if invalid)."""
     d = _desc(shape, lattice, order, tau_lb, knudsen, precision, False, True)
-    d.flags = _lib.FLAG_IN_PLACE if in_place else 0
+    d.flags = ((_lib.FLAG_IN_PLACE if in_place else 0)
+               | (_lib.FLAG_POPULATION_SWEEP if population_sweep else 0))
     return int(_lib.load().lkp_footprint_bytes(ctypes.byref(d)))
 
 
@@ -99,9 +101,15 @@ class Problem:
     def __init__(self, source, lattice: str, order: int, tau_lb=None, knudsen=None,
                  precision: str = "f64", subtract_mean: bool = False,
                  allow_unstable: bool = False, stream=None, population_sweep: bool = False,
-                 in_place: bool = False, drift=None):
+                 in_place: bool = False, drift=None, workspace=None):
         """drift: uniform drift (ux, uy, uz) in velocity-component order (x is the
-        last array axis) for the advection-diffusion variant; None = diffusion."""
+        last array axis) for the advection-diffusion variant; None = diffusion.
+
+        workspace: None, the library allocates the device state; True, the
+        state is placed in a byte tensor taken from torch's caching allocator
+        (freed back to torch when the problem closes); or a contiguous CUDA
+        tensor of at least ``footprint_bytes`` bytes, 256-byte aligned, that the
+        caller keeps and does not touch while the problem is open."""
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         if isinstance(source, torch.Tensor):
@@ -130,6 +138,20 @@ class Problem:
             for a, x in enumerate(u):
                 d.drift[a] = x
         self.lattice, self.order, self.precision = lattice, int(order), precision
+        self._ws = None
+        if workspace is not None and workspace is not False:
+            need = int(self._lib.lkp_footprint_bytes(ctypes.byref(d)))
+            if need <= 0:
+                check(self._lib.lkp_create(ctypes.byref(d), ctypes.byref(self._h)), "lkp_create")
+            if workspace is True:
+                ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+            else:
+                ws = workspace
+                if not (isinstance(ws, torch.Tensor) and ws.is_cuda and ws.is_contiguous()):
+                    raise ValueError("workspace must be a contiguous CUDA tensor")
+            d.workspace = ws.data_ptr()
+            d.workspace_bytes = ws.numel() * ws.element_size()
+            self._ws = ws
         check(self._lib.lkp_create(ctypes.byref(d), ctypes.byref(self._h)), "lkp_create")
         del src
 
@@ -138,6 +160,7 @@ class Problem:
         if getattr(self, "_h", None) and self._h.value:
             self._lib.lkp_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._ws = None   # the workspace outlives the handle
 
     def __del__(self):
         try:

@@ -36,7 +36,8 @@ class ProblemDesc(ctypes.Structure):
                 ("knudsen", ctypes.c_double), ("source", ctypes.c_void_p),
                 ("source_on_device", ctypes.c_int32), ("subtract_mean", ctypes.c_int32),
                 ("allow_unstable", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("drift", ctypes.c_double * 3)]
+                ("stream", ctypes.c_void_p), ("drift", ctypes.c_double * 3),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
 
 
 class SolveOpts(ctypes.Structure):

@@ -430,26 +430,121 @@ lkp_status tune_split(lkp_handle *h) {
 
 namespace {
 
-int64_t footprint_of(int precision, int Q, int64_t ncells, bool inplace = false) {
-  const int64_t nb = (ncells + 63) / 64 + 8;
-  const int64_t bufs = inplace ? 1 : 2;  // population (or correction) buffers
-  int64_t b = 3 * 8 * ncells + nb * NUM_NORMS * 8 + 4096;  // S + 2 Phi + partials + misc
-  if (precision == LKP_F64) b += bufs * 8 * (int64_t)Q * ncells;
-  else if (precision == LKP_F32) b += bufs * 4 * (int64_t)Q * ncells;
-  else if (precision == LKP_F32_IR)  // x, r, d, S32
-    b += 8 * (int64_t)Q * ncells + (1 + bufs) * 4 * (int64_t)Q * ncells + 4 * ncells;
-  else  // x, r, 2 x (BF16 n + FP32 Phi), S32
-    b += 8 * (int64_t)Q * ncells + 4 * (int64_t)Q * ncells + 2 * (2 * (int64_t)Q * ncells + 4 + 4 * ncells) +
-         4 * ncells;
-  return b;
+// Device memory of a handle: hipMalloc'd and owned by the handle, or carved
+// from a caller-provided workspace (256-byte aligned pieces); count_only
+// walks the same plan to measure it (lkp_footprint_bytes).
+struct DevAlloc {
+  char *base = nullptr;  // workspace, or null
+  size_t cap = 0;
+  size_t used = 0;
+  bool count_only = false;
+
+  lkp_status get(lkp_handle *h, void **p, size_t bytes) {
+    const size_t off = (used + 255) & ~size_t(255);
+    used = off + bytes;
+    if (count_only) {
+      *p = reinterpret_cast<void *>(uintptr_t(256));  // placeholder, never used
+      return LKP_OK;
+    }
+    if (base) {
+      if (used > cap)
+        return fail(LKP_ERR_ARG, "workspace of %zu bytes is too small (lkp_footprint_bytes: at least %zu)",
+                    cap, used);
+      *p = base + off;
+      return LKP_OK;
+    }
+    HIP_TRY(hipMalloc(p, bytes));
+    h->owned.push_back(*p);
+    return LKP_OK;
+  }
+  // Give back memory needed only while the handle is created (owned mode).
+  void drop(lkp_handle *h, void *p) {
+    if (base || count_only || !p) return;
+    auto it = std::find(h->owned.begin(), h->owned.end(), p);
+    if (it != h->owned.end()) {
+      (void)hipFree(p);
+      h->owned.erase(it);
+    }
+  }
+};
+
+template <class T>
+lkp_status dget(DevAlloc &A, lkp_handle *h, T **p, size_t bytes) {
+  void *v = nullptr;
+  lkp_status st = A.get(h, &v, bytes);
+  *p = static_cast<T *>(v);
+  return st;
 }
 
-lkp_status ensure_partials(lkp_handle *h, size_t nblocks) {
-  if (nblocks <= h->partial_cap) return LKP_OK;
-  if (h->partials) HIP_TRY(hipFree(h->partials));
-  h->partials = nullptr;
-  HIP_TRY(hipMalloc(&h->partials, nblocks * NUM_NORMS * sizeof(double)));
-  h->partial_cap = nblocks;
+unsigned partial_blocks(const lkp_handle *h);
+
+// Every device buffer of a handle, in one fixed order.  Create-time
+// temporaries of the stencil form (the FP64 source, and for FP32 its
+// stencil G) come back in tmp_S / tmp_G.
+lkp_status plan_state(lkp_handle *h, DevAlloc &A, double **tmp_S, double **tmp_G) {
+  const size_t n = h->ncells, Q = h->Q;
+  *tmp_S = *tmp_G = nullptr;
+  if (lkp_status st = dget(A, h, &h->norms_dev, NUM_NORMS * sizeof(double))) return st;
+  if (h->scalar) {
+    const size_t nb = partial_blocks(h);
+    if (lkp_status st = dget(A, h, &h->partials, nb * NUM_NORMS * sizeof(double))) return st;
+    h->partial_cap = nb;
+    if (lkp_status st = dget(A, h, tmp_S, n * 8)) return st;
+    if (lkp_status st = dget(A, h, tmp_G, n * 8)) return st;
+    const size_t fb = h->precision == LKP_F32 ? 4 : 8;
+    if (lkp_status st = dget(A, h, &h->f[0], n * fb)) return st;
+    if (h->precision != LKP_F32_IR)
+      if (lkp_status st = dget(A, h, &h->f[1], n * fb)) return st;
+    if (h->precision == LKP_F32) {
+      if (lkp_status st = dget(A, h, &h->S, n * 4)) return st;
+    } else {
+      h->S = *tmp_G;  // the stencil of the source is the state's G
+      *tmp_G = nullptr;
+    }
+    if (h->precision == LKP_F32_IR) {
+      if (lkp_status st = dget(A, h, &h->r32, n * 4)) return st;
+      if (lkp_status st = dget(A, h, &h->d32[0], n * 4)) return st;
+      if (lkp_status st = dget(A, h, &h->d32[1], n * 4)) return st;
+      if (lkp_status st = dget(A, h, &h->S32, n * 4)) return st;
+      if (lkp_status st = dget(A, h, &h->phi_dev, sizeof(double))) return st;
+    }
+    return LKP_OK;
+  }
+  // partial norms for the finest block split (P = 4: 64 cells per block)
+  const size_t nb = sweep_blocks(h, 4) + 8;
+  if (lkp_status st = dget(A, h, &h->partials, nb * NUM_NORMS * sizeof(double))) return st;
+  h->partial_cap = nb;
+  if (h->precision == LKP_F64 || h->precision == LKP_F32) {
+    const size_t fb = h->precision == LKP_F64 ? 8 : 4;
+    if (lkp_status st = dget(A, h, &h->f[0], Q * n * fb)) return st;
+    if (h->inplace) h->f[1] = h->f[0];
+    else if (lkp_status st = dget(A, h, &h->f[1], Q * n * fb)) return st;
+    if (lkp_status st = dget(A, h, &h->S, n * fb)) return st;
+  } else {
+    if (lkp_status st = dget(A, h, &h->f[0], Q * n * 8)) return st;  // x, the FP64 refined state
+    h->f[1] = nullptr;
+    if (lkp_status st = dget(A, h, &h->r32, Q * n * 4)) return st;
+    if (h->bf16dev()) {
+      const size_t words = (Q * n + 1) / 2;  // BF16 planes, cleared as 32-bit words
+      for (int k = 0; k < 2; ++k) {
+        if (lkp_status st = dget(A, h, &h->dn[k], words * 4)) return st;
+        if (lkp_status st = dget(A, h, &h->dphi[k], n * 4)) return st;
+      }
+    } else {
+      if (lkp_status st = dget(A, h, &h->d32[0], Q * n * 4)) return st;
+      if (h->inplace) {
+        h->d32[1] = h->d32[0];
+        if (lkp_status st = dget(A, h, &h->opp_dev, Q * sizeof(int))) return st;
+      } else if (lkp_status st = dget(A, h, &h->d32[1], Q * n * 4)) {
+        return st;
+      }
+    }
+    if (lkp_status st = dget(A, h, &h->S, n * 8)) return st;
+    if (lkp_status st = dget(A, h, &h->S32, n * 4)) return st;
+    if (lkp_status st = dget(A, h, &h->phi_dev, Q * sizeof(double))) return st;
+  }
+  if (lkp_status st = dget(A, h, &h->phib[0], n * 8)) return st;
+  if (lkp_status st = dget(A, h, &h->phib[1], n * 8)) return st;
   return LKP_OK;
 }
 
@@ -594,25 +689,15 @@ lkp_status upload_coefficients(lkp_handle *h) {
     h->c32[i] = (float)h->c64[i];
     h->c32[Q + i] = (float)h->chi[i];
   }
-  if (h->refined() && !h->scalar) {
-    HIP_TRY(hipMalloc(&h->phi_dev, Q * sizeof(double)));
+  if (h->refined() && !h->scalar)
     HIP_TRY(hipMemcpy(h->phi_dev, h->phi.data(), Q * sizeof(double), hipMemcpyHostToDevice));
-  }
   return LKP_OK;
 }
 
 void release(lkp_handle *h) {
   drop_graphs(h);
-  void *ptrs[] = {h->f[0],    h->f[1],    h->S,       h->S32,     h->phi_dev,
-                  h->r32,     h->d32[0],  h->d32[1],  h->dn[0],   h->dn[1],
-                  h->dphi[0], h->dphi[1], h->phib[0], h->phib[1], h->partials,
-                  h->norms_dev};
-  for (size_t k = 0; k < sizeof ptrs / sizeof ptrs[0]; ++k) {  // in place, two slots share a buffer
-    bool seen = false;
-    for (size_t j = 0; j < k; ++j) seen = seen || ptrs[j] == ptrs[k];
-    if (ptrs[k] && !seen) (void)hipFree(ptrs[k]);
-  }
-  if (h->opp_dev) (void)hipFree(h->opp_dev);
+  for (void *p : h->owned) (void)hipFree(p);  // a caller's workspace is not ours to free
+  h->owned.clear();
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   if (h->capture) (void)hipStreamDestroy(h->capture);
 }
@@ -755,17 +840,9 @@ unsigned partial_blocks(int lattice, const int64_t n[3]) {
 
 unsigned partial_blocks(const lkp_handle *h) { return partial_blocks(h->lattice, h->n); }
 
-// Device bytes of a stencil-form (omega = 1) handle: Phi twice, G, the FP64
-// source, norms; F32_IR adds four FP32 fields.
-int64_t scalar_footprint(int precision, int lattice, const int64_t n3[3]) {
-  const int64_t n = n3[0] * n3[1] * n3[2];
-  int64_t b = 8 * n * (precision == LKP_F32 ? 3 : 4) + (int64_t)partial_blocks(lattice, n3) * NUM_NORMS * 8 + 4096;
-  if (precision == LKP_F32_IR) b += 4 * 4 * n;
-  return b;
-}
-
-lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::vector<double> &S) {
-  (void)d;
+// Fill a stencil-form handle whose device memory was just planned.
+lkp_status create_scalar(lkp_handle *h, DevAlloc &A, double *S_dev, double *G_dev,
+                         const std::vector<double> &S) {
   {  // phi_i and chi_i must be equal on every orbit for per-orbit stencil weights
     const VelTable T = velocity_table(h->lattice);
     const VelMaps M = build_maps(T);
@@ -779,52 +856,35 @@ lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::ve
   }
   const size_t n = h->ncells;
   h->S_host = S;
-  const int64_t nb = partial_blocks(h);
-  h->footprint = scalar_footprint(h->precision, h->lattice, h->n);
-  HIP_TRY(hipMalloc(&h->norms_dev, NUM_NORMS * sizeof(double)));
-  HIP_TRY(hipHostMalloc(&h->norms_host, NUM_NORMS * sizeof(double), hipHostMallocDefault));
-  if (lkp_status st = ensure_partials(h, nb)) return st;
   if (lkp_status st = upload_coefficients(h)) return st;
   // G = sum_i chi_i S(x - v_i), once, with the FP64 stencil
-  double *S_dev = nullptr, *G_dev = nullptr;
-  HIP_TRY(hipMalloc(&S_dev, n * 8));
-  HIP_TRY(hipMalloc(&G_dev, n * 8));
+  double *G = G_dev ? G_dev : (double *)h->S;
   HIP_TRY(hipMemcpy(S_dev, S.data(), n * 8, hipMemcpyHostToDevice));
   StencilParams p = stencil_params(h);
   orbit_weights(h, h->chi, false, &p);
   p.xin = S_dev;
-  p.xout = G_dev;
+  p.xout = G;
   p.src = nullptr;
   HIP_TRY(launch_stencil(h->lattice, SMODE_F64, 0, p, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
-  HIP_TRY(hipFree(S_dev));
-  const size_t fb = h->precision == LKP_F32 ? 4 : 8;
-  HIP_TRY(hipMalloc(&h->f[0], n * fb));
-  if (h->precision != LKP_F32_IR) HIP_TRY(hipMalloc(&h->f[1], n * fb));
+  A.drop(h, S_dev);
   if (h->precision == LKP_F32) {
-    HIP_TRY(hipMalloc(&h->S, n * 4));
-    HIP_TRY(launch_f64_to_f32(G_dev, (float *)h->S, n, h->stream));
+    HIP_TRY(launch_f64_to_f32(G, (float *)h->S, n, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(hipFree(G_dev));
+    A.drop(h, G_dev);
     HIP_TRY(launch_fill_f32((float *)h->f[0], 0.0f, n, h->stream));
   } else {
-    h->S = G_dev;
     HIP_TRY(launch_fill_f64((double *)h->f[0], 0.0, n, h->stream));
   }
   if (h->precision == LKP_F32_IR) {
-    HIP_TRY(hipMalloc(&h->r32, n * 4));
-    HIP_TRY(hipMalloc(&h->d32[0], n * 4));
-    HIP_TRY(hipMalloc(&h->d32[1], n * 4));
-    HIP_TRY(hipMalloc(&h->S32, n * 4));
     HIP_TRY(launch_f64_to_f32((const double *)h->S, h->S32, n, h->stream));
     // residual of x = 0 is G
-    std::vector<double> G(n);
-    HIP_TRY(hipMemcpy(G.data(), h->S, n * 8, hipMemcpyDeviceToHost));
+    std::vector<double> Gh(n);
+    HIP_TRY(hipMemcpy(Gh.data(), h->S, n * 8, hipMemcpyDeviceToHost));
     long double g2 = 0;
-    for (double v : G) g2 += (long double)v * v;
+    for (double v : Gh) g2 += (long double)v * v;
     h->g_norm = (double)std::sqrt(g2);
     const double one = 1.0;
-    HIP_TRY(hipMalloc(&h->phi_dev, sizeof(double)));
     HIP_TRY(hipMemcpy(h->phi_dev, &one, sizeof(double), hipMemcpyHostToDevice));
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -833,7 +893,9 @@ lkp_status create_scalar(const lkp_problem_desc *d, lkp_handle *h, const std::ve
   return tune_stencil(h);
 }
 
-lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
+// Host-side set-up of a handle from a description: validation, constants,
+// the stencil / in-place choice (no device memory, no source).
+lkp_status init_handle(const lkp_problem_desc *d, lkp_handle *h) {
   LatticeConstants lc;
   double tau;
   if (lkp_status st = validate_desc(d, &lc, &tau)) return st;
@@ -874,7 +936,33 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   }
   h->simple_wrap = h->n[0] >= max_component(lc.table, 0) && h->n[1] >= max_component(lc.table, 1) &&
                    h->n[2] >= max_component(lc.table, 2);
+  // omega = 1 exactly: run the scalar stencil form unless populations are asked
+  // for (or a drift makes phi_i differ within a velocity orbit)
+  h->scalar = (h->omega == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP) && !h->drift;
+  if (h->scalar && h->bf16dev())
+    return fail(LKP_ERR_UNSUPPORTED,
+                "BF16DEV_IR at tau_lb = 1: the stencil form keeps no populations (the deviation "
+                "is exactly chi_i S); set LKP_FLAG_POPULATION_SWEEP or use F32_IR");
+  h->inplace = !h->scalar && (d->flags & LKP_FLAG_IN_PLACE) != 0;
+  if (h->inplace && h->bf16dev())
+    return fail(LKP_ERR_UNSUPPORTED, "LKP_FLAG_IN_PLACE is not available for BF16DEV_IR");
+  return LKP_OK;
+}
 
+// Bytes the description's device memory takes (the allocation plan walked
+// without allocating); 0 if the description is invalid.
+int64_t plan_bytes(const lkp_problem_desc *d) {
+  lkp_handle h;
+  if (init_handle(d, &h) != LKP_OK) return 0;
+  DevAlloc A;
+  A.count_only = true;
+  double *ts = nullptr, *tg = nullptr;
+  if (plan_state(&h, A, &ts, &tg) != LKP_OK) return 0;
+  return (int64_t)A.used;
+}
+
+lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
+  if (lkp_status st = init_handle(d, h)) return st;
   // source: host copy, mean check, scaling S = s c_s^2 (tau_lb - 1/2)
   if (!d->source) return fail(LKP_ERR_ARG, "null source");
   const size_t n = h->ncells;
@@ -901,61 +989,36 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
   std::vector<double> S(n);
   for (size_t c = 0; c < n; ++c) S[c] = (remove ? s[c] - mean : s[c]) * scale;
 
-  // omega = 1 exactly: run the scalar stencil form unless populations are asked
-  // for (or a drift makes phi_i differ within a velocity orbit)
-  h->scalar = (h->omega == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP) && !h->drift;
-  if (h->scalar && h->bf16dev())
-    return fail(LKP_ERR_UNSUPPORTED,
-                "BF16DEV_IR at tau_lb = 1: the stencil form keeps no populations (the deviation "
-                "is exactly chi_i S); set LKP_FLAG_POPULATION_SWEEP or use F32_IR");
-  if (h->scalar) return create_scalar(d, h, S);
-  h->inplace = (d->flags & LKP_FLAG_IN_PLACE) != 0;
-  if (h->inplace && h->bf16dev())
-    return fail(LKP_ERR_UNSUPPORTED, "LKP_FLAG_IN_PLACE is not available for BF16DEV_IR");
+  // device memory: the caller's workspace, or owned allocations
+  if (d->workspace && d->workspace_bytes <= 0) return fail(LKP_ERR_ARG, "workspace without a size");
+  if (!d->workspace && d->workspace_bytes != 0) return fail(LKP_ERR_ARG, "workspace size without a workspace");
+  DevAlloc A;
+  A.base = static_cast<char *>(d->workspace);
+  A.cap = d->workspace ? (size_t)d->workspace_bytes : 0;
+  if (A.base && (reinterpret_cast<uintptr_t>(A.base) & 255))
+    return fail(LKP_ERR_ARG, "workspace must be 256-byte aligned");
+  double *tmp_S = nullptr, *tmp_G = nullptr;
+  if (lkp_status st = plan_state(h, A, &tmp_S, &tmp_G)) return st;
+  h->footprint = (int64_t)A.used;  // the plan's size, owned or in the workspace
+  h->external = A.base != nullptr;
+  HIP_TRY(hipHostMalloc(&h->norms_host, NUM_NORMS * sizeof(double), hipHostMallocDefault));
+  if (h->scalar) return create_scalar(h, A, tmp_S, tmp_G, S);
 
-  // device memory
   const size_t Q = h->Q;
-  h->footprint = footprint_of(h->precision, h->Q, h->ncells, h->inplace);
   if (h->precision == LKP_F64) {
-    HIP_TRY(hipMalloc(&h->f[0], Q * n * 8));
-    if (h->inplace) h->f[1] = h->f[0];
-    else HIP_TRY(hipMalloc(&h->f[1], Q * n * 8));
-    HIP_TRY(hipMalloc(&h->S, n * 8));
     HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
   } else if (h->precision == LKP_F32) {
-    HIP_TRY(hipMalloc(&h->f[0], Q * n * 4));
-    if (h->inplace) h->f[1] = h->f[0];
-    else HIP_TRY(hipMalloc(&h->f[1], Q * n * 4));
     std::vector<float> S32(n);
     for (size_t c = 0; c < n; ++c) S32[c] = (float)S[c];
-    HIP_TRY(hipMalloc(&h->S, n * 4));
     HIP_TRY(hipMemcpy(h->S, S32.data(), n * 4, hipMemcpyHostToDevice));
   } else {
-    HIP_TRY(hipMalloc(&h->f[0], Q * n * 8));  // x, the FP64 refined state
-    h->f[1] = nullptr;
-    HIP_TRY(hipMalloc(&h->r32, Q * n * 4));
-    if (h->bf16dev()) {
-      const size_t words = (Q * n + 1) / 2;  // BF16 planes, cleared as 32-bit words
-      for (int k = 0; k < 2; ++k) {
-        HIP_TRY(hipMalloc(&h->dn[k], words * 4));
-        HIP_TRY(hipMalloc(&h->dphi[k], n * 4));
-      }
-    } else {
-      HIP_TRY(hipMalloc(&h->d32[0], Q * n * 4));
-      if (h->inplace) {
-        h->d32[1] = h->d32[0];
-        const VelTable T = velocity_table(h->lattice);
-        const VelMaps M = build_maps(T);
-        std::vector<int> opp(Q);
-        for (size_t i = 0; i < Q; ++i)
-          opp[i] = M.vidx[6 - T.v[i][0]][6 - T.v[i][1]][6 - T.v[i][2]];
-        HIP_TRY(hipMalloc(&h->opp_dev, Q * sizeof(int)));
-        HIP_TRY(hipMemcpy(h->opp_dev, opp.data(), Q * sizeof(int), hipMemcpyHostToDevice));
-      } else {
-        HIP_TRY(hipMalloc(&h->d32[1], Q * n * 4));
-      }
+    if (h->inplace && !h->bf16dev()) {
+      const VelTable T = velocity_table(h->lattice);
+      const VelMaps M = build_maps(T);
+      std::vector<int> opp(Q);
+      for (size_t i = 0; i < Q; ++i) opp[i] = M.vidx[6 - T.v[i][0]][6 - T.v[i][1]][6 - T.v[i][2]];
+      HIP_TRY(hipMemcpy(h->opp_dev, opp.data(), Q * sizeof(int), hipMemcpyHostToDevice));
     }
-    HIP_TRY(hipMalloc(&h->S, n * 8));
     HIP_TRY(hipMemcpy(h->S, S.data(), n * 8, hipMemcpyHostToDevice));
     std::vector<float> S32(n);
     long double s2 = 0, c2 = 0;
@@ -965,15 +1028,8 @@ lkp_status create_impl(const lkp_problem_desc *d, lkp_handle *h) {
     }
     for (int i = 0; i < h->Q; ++i) c2 += (long double)h->chi[i] * h->chi[i];
     h->g_norm = (double)std::sqrt(s2 * c2);
-    HIP_TRY(hipMalloc(&h->S32, n * 4));
     HIP_TRY(hipMemcpy(h->S32, S32.data(), n * 4, hipMemcpyHostToDevice));
   }
-  HIP_TRY(hipMalloc(&h->phib[0], n * 8));
-  HIP_TRY(hipMalloc(&h->phib[1], n * 8));
-  HIP_TRY(hipMalloc(&h->norms_dev, NUM_NORMS * sizeof(double)));
-  HIP_TRY(hipHostMalloc(&h->norms_host, NUM_NORMS * sizeof(double), hipHostMallocDefault));
-  // partial norms for the finest block split (P = 4: 64 cells per block)
-  if (lkp_status st = ensure_partials(h, sweep_blocks(h, 4) + 8)) return st;
   if (lkp_status st = upload_coefficients(h)) return st;
 
   // initial state f* = 0 (fill kernels, not memset), Phi buffers = 0
@@ -1036,17 +1092,10 @@ extern "C" {
 const char *lkp_last_error(void) { return lkp::rt::last_error(); }
 
 int64_t lkp_footprint_bytes(const lkp_problem_desc *d) {
-  LatticeConstants lc;
-  double tau;
   const std::string keep = lkp::rt::last_error();
-  if (validate_desc(d, &lc, &tau) != LKP_OK) {
-    lkp::rt::fail(LKP_OK, "%s", keep.c_str());
-    return 0;
-  }
-  const bool scalar = (1.0 / tau == 1.0) && !(d->flags & LKP_FLAG_POPULATION_SWEEP) && !has_drift(d);
-  if (scalar) return scalar_footprint(d->precision, d->lattice, d->n);
-  return footprint_of(d->precision, lc.table.q, d->n[0] * d->n[1] * d->n[2],
-                      (d->flags & LKP_FLAG_IN_PLACE) != 0);
+  const int64_t b = plan_bytes(d);
+  if (b == 0) lkp::rt::fail(LKP_OK, "%s", keep.c_str());
+  return b;
 }
 
 lkp_status lkp_create(const lkp_problem_desc *d, lkp_handle **out) {

@@ -111,7 +111,9 @@ struct lkp_handle {
   double *norms_dev = nullptr;
   double *norms_host = nullptr;  // pinned
   int64_t total_sweeps = 0;
-  int64_t footprint = 0;
+  int64_t footprint = 0;     // device bytes of the state (the allocation plan's size)
+  bool external = false;     // the state lives in a caller's workspace
+  std::vector<void *> owned; // device allocations the handle frees
   int split = 1;
   bool tuned = false;
   int stile = 0;            // 3D stencil form: tile variant and block order (tune_stencil)

@@ -76,12 +76,16 @@ def percentile(xs, q):
 class GpuBackend:
     """Resident problems on the GPU through the lkp library."""
 
-    def __init__(self, precision: str = "f32_ir", keep_phi: bool = False):
+    def __init__(self, precision: str = "f32_ir", keep_phi: bool = False, workspace: bool = True):
+        """workspace: place each problem's state in a tensor from torch's
+        caching allocator (admission and retirement then reuse cached device
+        memory instead of allocating and freeing it each time)."""
         import paper_1504_05869_amd as lkp
         from . import workloads as W
         self.lkp, self.W = lkp, W
         self.precision = precision
         self.keep_phi = keep_phi
+        self.workspace = bool(workspace)
         self.groups = {}
 
     def footprint(self, req: Request) -> int:
@@ -91,7 +95,7 @@ class GpuBackend:
     def admit(self, req: Request, tol: float, max_sweeps: int):
         s = self.W.poisson_source(req.kind, req.shape, seed=req.seed)
         p = self.lkp.Problem(s, req.lattice, req.order, knudsen=req.knudsen,
-                             precision=self.precision)
+                             precision=self.precision, workspace=True if self.workspace else None)
         key = (req.lattice, req.order)
         g = self.groups.get(key)
         if g is None:
