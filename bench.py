@@ -130,18 +130,29 @@ def oracle_fixed_point(lattice, order, s, tau_lb=None, knudsen=None):
 
 
 def timed_solve(lkp, torch, s, lattice, order, precision, tol, ref=None, check_every=100,
-                **kw) -> dict:
+                chunk=0, label="", **kw) -> dict:
     """Solve to estimated rel-L2 `tol`; wall time, sweeps, the solver's own
-    estimate and, with `ref`, the true error against the oracle's fixed point."""
+    estimate and, with `ref`, the true error against the oracle's fixed point.
+    chunk > 0: consecutive lkp_solve calls of at most `chunk` sweeps (a resumed
+    call keeps the convergence history, a stopped refinement its partial
+    correction), one progress line each."""
     with lkp.Problem(s, lattice, order, precision=precision, **kw) as q:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rep = q.solve(tol_rel_l2=tol, check_every=check_every, max_sweeps=4_000_000,
-                      raise_on_error=False)
+        sweeps, outer = 0, 0
+        while True:
+            rep = q.solve(tol_rel_l2=tol, check_every=check_every,
+                          max_sweeps=chunk if chunk > 0 else 4_000_000, raise_on_error=False)
+            sweeps += rep["sweeps"]
+            outer = rep["outer"] if precision in ("f64", "f32") else outer + rep["outer"]
+            if chunk <= 0 or rep["status"] == 0 or sweeps >= 4_000_000:
+                break
+            say(f"{label} {precision}: {sweeps} sweeps {time.perf_counter() - t1:.0f} s "
+                f"est {rep['est_rel_err']:.3e}")
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         out = {"precision": precision, "tol_rel_l2": tol, "seconds": round(el, 4),
-               "sweeps": rep["sweeps"], "outer": rep["outer"], "status": rep["status"],
+               "sweeps": sweeps, "outer": outer, "status": rep["status"],
                "est_rel_err": rep["est_rel_err"]}
         if ref is not None:
             out["true_rel_l2"] = true_rel_l2(q.phi_host(), ref)
@@ -520,7 +531,8 @@ def configs_matrix(lkp, torch, W) -> dict:
     abl = []
     for prec in ("bf16dev_ir", "f32_ir"):
         r = timed_solve(lkp, torch, s3, "D3Q111", 5, prec, 1e-6, ref=ref3, check_every=200,
-                        tau_lb=1.0, population_sweep=True)
+                        chunk=2000, label="[configs] 256^3 population sweep", tau_lb=1.0,
+                        population_sweep=True)
         say(f"[configs] 256^3 population sweep {prec}: {r['seconds']} s, true {r['true_rel_l2']:.2e}")
         abl.append(r)
     return {"c2_1024x1024": rows, "c3_256cubed_population_sweep": abl}
@@ -578,9 +590,6 @@ def main():
     if args.configs:
         print(json.dumps({"configs": configs_matrix(lkp, torch, W)}), flush=True)
         return
-    if args.rates_only:
-        print(json.dumps({"sweeps": extras_rates(lkp, torch, W, args.only)}), flush=True)
-        return
     if args.calibrate_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
@@ -588,6 +597,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    if args.rates_only:
+        print(json.dumps({"sweeps": extras_rates(lkp, torch, W, args.only)}), flush=True)
+        return
 
     if args.skip_headline:
         out = {}

@@ -149,8 +149,8 @@ typedef struct lkp_problem_desc {
 
 typedef struct lkp_handle lkp_handle;
 
-/* Create a problem (the BGK scheme of Sec. 3 on the set and order of Sec. 4,
- * source term of Sec. 5): validates the description, computes the set's
+/* Create a problem (the discrete BGK scheme of Sec. 2, Eq. boltzmann, on the
+ * set and equilibrium order of Sec. 4, source term of Sec. 5): validates the description, computes the set's
  * weights, c_s^2, phi_i, chi_i (long double, rounded once), scales the source
  * S = s c_s^2 (tau_lb - 1/2), places the device state (two population
  * buffers, S, Phi buffers, reduction partials) and sets f* = 0.
@@ -213,7 +213,12 @@ typedef struct lkp_solve_report {
  * NULL. */
 lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *rep);
 
-/* Advance exactly `sweeps` sweeps (>= 0).  The last sweep stores Phi. */
+/* Advance exactly `sweeps` sweeps (>= 0): each is one step of the discrete
+ * BGK relaxation with source (Sec. 2, Eq. boltzmann, with the equilibrium and
+ * source shapes of Sec. 4 and the scaled source of Sec. 5): pull-stream,
+ * moment Phi = sum_i f_i, collide.  No stopping test; the last sweep stores
+ * Phi.  Errors: LKP_ERR_ARG (sweeps < 0), LKP_ERR_STATE (the handle is
+ * resident in a group: the group steps it), LKP_ERR_HIP. */
 lkp_status lkp_step(lkp_handle *h, int64_t sweeps);
 
 typedef struct lkp_residual_report {
@@ -226,8 +231,11 @@ typedef struct lkp_residual_report {
   int64_t sweeps;         /* sweeps since creation */
 } lkp_residual_report;
 
-/* Residual of the current state in FP64 on the GPU, without advancing it
- * (needs at least one sweep done: LKP_ERR_STATE otherwise). */
+/* Residual of the current state in FP64 on the GPU, without advancing it:
+ * the distance from the steady state that Sec. 4 and 5 take as the Poisson
+ * solution (all time derivatives zero, Sec. 3), measured as one sweep's change
+ * of Phi and of the populations.  Needs at least one sweep done
+ * (LKP_ERR_STATE otherwise); `r` is written only on success. */
 lkp_status lkp_residual(lkp_handle *h, lkp_residual_report *r);
 
 /* Phi of the last sweep (post-stream moment, Sec. 2: Phi = sum_i f_i), n FP64

@@ -23,6 +23,7 @@
 #include "constants.hpp"
 #include "dev_kernels.hpp"
 #include "kernels.hpp"
+#include "stencil.hpp"
 #include "runtime.hpp"
 
 using namespace lkp;
@@ -741,6 +742,8 @@ StencilParams stencil_params(const lkp_handle *h) {
 // the default (the velocity-by-velocity tile 0).
 lkp_status tune_stencil(lkp_handle *h) {
   if (h->dim != 3) return LKP_OK;
+  h->stile = kStencilDefault3;
+  h->sremap = 0;
   const char *ft = std::getenv("LKP_STENCIL_TILE");
   const char *fr = std::getenv("LKP_STENCIL_REMAP");
   if (ft || fr) {
@@ -786,7 +789,10 @@ lkp_status tune_stencil(lkp_handle *h) {
       for (int ri = 0; ri < 3; ++ri) {
         p.tile = (unsigned)t;
         p.remap = kRemaps[ri];
-        LKP_HIP_TRY(launch_stencil(h->lattice, smode, 0, p, h->stream));
+        if (launch_stencil(h->lattice, smode, 0, p, h->stream) == hipErrorInvalidValue) {
+          worst[t][ri] = 1e30f;  // a variant this set does not take (returned before launching)
+          continue;
+        }
         LKP_HIP_TRY(hipEventRecord(e0, h->stream));
         for (int k = 0; k < 5; ++k) LKP_HIP_TRY(launch_stencil(h->lattice, smode, 0, p, h->stream));
         LKP_HIP_TRY(hipEventRecord(e1, h->stream));

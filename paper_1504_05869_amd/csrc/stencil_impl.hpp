@@ -22,6 +22,7 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "stencil.hpp"
 #include "lattices.hpp"
 
 namespace lkp {
@@ -336,6 +337,18 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
 #pragma unroll
         for (int j = 0; j < NST; ++j)
           if (j + 1 < NST || (int)threadIdx.x + 256 * j < NL) t[threadIdx.x + 256 * j] = pre[j];
+        // source values of this step's output plane, loaded before the next
+        // plane's prefetch (waiting for them must not wait for the prefetch)
+        const int m = step - 2 * VMZ;
+        const int gz = z0 + m;
+        TC sv[CY];
+#pragma unroll
+        for (int k = 0; k < CY; ++k) {
+          sv[k] = (TC)0;
+          const int gy = y0 + ly0 + k;
+          if (src && m >= 0 && gz < nz && gx < nx && gy < ny)
+            sv[k] = (TC)src[((size_t)gz * ny + gy) * nx + gx];
+        }
         __syncthreads();
         if (step + 1 < NSTEPS) fetch(step + 1);
         if constexpr (CENTRE) {
@@ -441,8 +454,6 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
         }
         // output plane m = step - 2 VMZ is complete
         constexpr int fs = (ph + 1) % NZR;
-        const int m = step - 2 * VMZ;
-        const int gz = z0 + m;
         if (m >= 0 && gz < nz) {
 #pragma unroll
           for (int k = 0; k < CY; ++k) {
@@ -450,7 +461,7 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
             if (gx < nx && gy < ny) {
               const size_t c = ((size_t)gz * ny + gy) * nx + gx;
               TC out = acc[fs][k];
-              if (src) out = out + (TC)src[c];
+              if (src) out = out + sv[k];
               if constexpr (MT::RESID) {
                 const double r = (double)out - (double)cen[fs][k];  // R = A X + G - X
                 xout[c] = (TOUT)r;
@@ -487,11 +498,258 @@ __global__ void __launch_bounds__(256) k_stencil3(StencilParams p) {
   if constexpr ((FLAGS & FLAG_REDUCE) != 0) block_norms(v, p.partials + (size_t)lin * NUM_NORMS);
 }
 
+// Two adjacent values, read or written as one 2-element access (16 bytes in
+// FP64: one ds_read_b128 from LDS).
+template <class T>
+struct alignas(2 * sizeof(T)) Pair2 {
+  T a, b;
+};
+
+// Plane-sum form of the 3D stencil for sets of whole shells.  With
+// S_d f(x) = f(x + d) + f(x - d) (S_0 f = f) the stencil is
+//   Phi'(z) = sum_c S_c^z T_c,   T_c = sum_{a,b} w[a,b,c] S_b^y S_a^x Phi,
+// and T_c of one input plane serves the outputs at z +- c.  A block owns
+// 64 x (8 CY) x BZ output cells; a thread owns two adjacent x cells on CY
+// rows.  Per staged input plane it reads, for each of its CY + 2 VMY rows,
+// the 2 + 2 VMX values around its pair with 2-element LDS reads, forms the
+// x sums in registers, and accumulates T_c for its cells (rows in y order,
+// then a in order), so a plane costs one barrier and about half the LDS bytes
+// of the separable form.  The output ring then takes T_0 into plane z and
+// T_c into planes z +- c, input planes in z order.  The summation order of
+// every output cell is the same for every CY and BZ, so the variants of this
+// family give the same bits; it rounds differently from the other families.
+template <int LID, int SM, int FLAGS, int CY, int BZ>
+__global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
+  // planes fetched ahead into registers (two, with the unroll that needs,
+  // pushed the FP64 variants past 256 VGPRs)
+  constexpr int PD = 1;
+  using SP = SepPlan3<LID>;
+  using L = Lattice<LID>;
+  using MT = SModeTraits<SM>;
+  using TIN = typename MT::TIN;
+  using TOUT = typename MT::TOUT;
+  using TSRC = typename MT::TSRC;
+  using TC = typename MT::TC;
+  constexpr int VMX = L::VMX, VMY = L::VMY, VMZ = L::VMZ;
+  constexpr int TX = 64, NG = 8, TY = NG * CY;  // 32 cell pairs x 8 row groups
+  constexpr int NZR = 2 * VMZ + 1;
+  constexpr int LX = TX + 2 * VMX, LY = TY + 2 * VMY, NL = LX * LY;
+  constexpr int NST = (NL + 255) / 256;
+  constexpr int NSTEPS = BZ + 2 * VMZ;
+  constexpr int SEG = 2 + 2 * VMX;  // staged values around a cell pair
+  constexpr int NR = CY + 2 * VMY;  // staged rows a thread reads
+  constexpr bool CENTRE = MT::RESID || (FLAGS & FLAG_REDUCE) != 0;
+  static_assert(SP::t.closed, "the plane-sum form needs a set of whole shells");
+  static_assert(LX % 2 == 0 && NL % 2 == 0, "2-element LDS reads need even rows");
+  __shared__ __align__(16) TIN tile[2][NL];
+
+  const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
+  const unsigned nb = gridDim.x;
+  const unsigned lin = p.remap ? xcd_runs(blockIdx.x, nb, p.remap) : blockIdx.x;
+  const unsigned bxi = lin % p.gbx, byi = (lin / p.gbx) % p.gby, bzi = lin / (p.gbx * p.gby);
+  const int x0 = (int)bxi * TX, y0 = (int)byi * TY, z0 = (int)bzi * BZ;
+  const unsigned pcells = (unsigned)nx * (unsigned)ny;
+  const TIN *__restrict__ xin = reinterpret_cast<const TIN *>(p.xin);
+
+  unsigned soff[NST];
+#pragma unroll
+  for (int j = 0; j < NST; ++j) {
+    const int e = (int)threadIdx.x + 256 * j;
+    const int lx = e % LX, ly = e / LX;
+    soff[j] = (e < NL) ? (unsigned)(pmod(y0 + ly - VMY, ny) * nx + pmod(x0 + lx - VMX, nx)) : 0u;
+  }
+  // PD register sets of prefetched planes: plane `step` sits in set step % PD
+  TIN pre[PD][NST];
+  auto fetch = [&](auto PIc, int step) __attribute__((always_inline)) {
+    constexpr int pi = (int)PIc;
+    const unsigned base = (unsigned)pmod(z0 - VMZ + step, nz) * pcells;
+#pragma unroll
+    for (int j = 0; j < NST; ++j)
+      if (j + 1 < NST || (int)threadIdx.x + 256 * j < NL) pre[pi][j] = xin[base + soff[j]];
+  };
+
+  const int ip = (int)(threadIdx.x % 32);  // cell pair
+  const int g = (int)(threadIdx.x / 32);   // row group
+  const int gx = x0 + 2 * ip;
+  TC acc[NZR][CY][2];
+#pragma unroll
+  for (int j = 0; j < NZR; ++j)
+#pragma unroll
+    for (int k = 0; k < CY; ++k) acc[j][k][0] = acc[j][k][1] = (TC)0;
+
+  double v[NUM_NORMS] = {0, 0, 0, 0, 0, 0};
+  const TSRC *__restrict__ src = reinterpret_cast<const TSRC *>(p.src);
+  TOUT *__restrict__ xout = reinterpret_cast<TOUT *>(p.xout);
+
+  static_for<0, PD>([&](auto PI) __attribute__((always_inline)) {
+    if ((int)PI < NSTEPS) fetch(PI, (int)PI);
+  });
+  // steps unrolled by NZR * PD: ring slots and prefetch sets are static
+  for (int s0 = 0; s0 < NSTEPS; s0 += NZR * PD) {
+    static_for<0, NZR * PD>([&](auto PHX) __attribute__((always_inline)) {
+      constexpr int ph = (int)PHX % NZR;
+      constexpr int pi = (int)PHX % PD;
+      const int step = s0 + (int)PHX;
+      if (step < NSTEPS) {  // block-uniform
+        TIN *t = tile[step & 1];
+#pragma unroll
+        for (int j = 0; j < NST; ++j)
+          if (j + 1 < NST || (int)threadIdx.x + 256 * j < NL) t[threadIdx.x + 256 * j] = pre[pi][j];
+        // the source (and centre) values of this step's output plane are
+        // loaded before the next plane's prefetch, so that waiting for them
+        // at the output does not also wait for the prefetch
+        const int m = step - 2 * VMZ;
+        const int gz = z0 + m;
+        const bool emit = m >= 0 && gz < nz;
+        TC sv[CY][2], cv[CY][2];
+#pragma unroll
+        for (int k = 0; k < CY; ++k)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            sv[k][q] = cv[k][q] = (TC)0;
+            const int gy = y0 + g * CY + k;
+            if (emit && gy < ny && gx + q < nx) {
+              const size_t c = ((size_t)gz * ny + gy) * nx + gx + q;
+              if (src) sv[k][q] = (TC)src[c];
+              if constexpr (CENTRE) cv[k][q] = (TC)xin[c];
+            }
+          }
+        __syncthreads();
+        if (step + PD < NSTEPS) fetch(std::integral_constant<int, pi>{}, step + PD);
+
+        TC T[VMZ + 1][CY][2];
+#pragma unroll
+        for (int c = 0; c <= VMZ; ++c)
+#pragma unroll
+          for (int k = 0; k < CY; ++k) T[c][k][0] = T[c][k][1] = (TC)0;
+        // rows are read one ahead: the reads of row r + 1 are in flight
+        // while row r's multiply-adds run
+        const TIN *rowbase = t + g * CY * LX + 2 * ip;
+        TIN seg[2][SEG];
+        auto read_row = [&](auto Rc) __attribute__((always_inline)) {
+          constexpr int r = (int)Rc;
+#pragma unroll
+          for (int e = 0; e < SEG; e += 2) {
+            const Pair2<TIN> q = *reinterpret_cast<const Pair2<TIN> *>(rowbase + r * LX + e);
+            seg[r & 1][e] = q.a;
+            seg[r & 1][e + 1] = q.b;
+          }
+        };
+        read_row(std::integral_constant<int, 0>{});
+        static_for<0, NR>([&](auto R) __attribute__((always_inline)) {
+          constexpr int r = (int)R;
+          if constexpr (r + 1 < NR) read_row(std::integral_constant<int, r + 1>{});
+          // x sums of the two cells: X[a][q] = S_a^x Phi at cell q
+          TC X[VMX + 1][2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            X[0][q] = (TC)seg[r & 1][VMX + q];
+#pragma unroll
+            for (int a = 1; a <= VMX; ++a)
+              X[a][q] = (TC)seg[r & 1][VMX + q + a] + (TC)seg[r & 1][VMX + q - a];
+          }
+          static_for<0, CY>([&](auto K) __attribute__((always_inline)) {
+            constexpr int k = (int)K;
+            constexpr int dy = r - VMY - k;  // y offset of this row for output row k
+            constexpr int b = dy < 0 ? -dy : dy;
+            if constexpr (b <= VMY) {
+              static_for<0, VMZ + 1>([&](auto Cz) __attribute__((always_inline)) {
+                constexpr int c = (int)Cz;
+                static_for<0, VMX + 1>([&](auto A) __attribute__((always_inline)) {
+                  constexpr int a = (int)A;
+                  constexpr int o = SP::t.orb[a][b][c];
+                  if constexpr (o >= 0) {
+                    TC w;
+                    if constexpr (sizeof(TC) == 8) w = (TC)p.coef.d[o];
+                    else w = (TC)p.coef.f[o];
+                    T[c][k][0] = FmaT<SM>::f(w, X[a][0], T[c][k][0]);
+                    T[c][k][1] = FmaT<SM>::f(w, X[a][1], T[c][k][1]);
+                  }
+                });
+              });
+            }
+          });
+          // compiler-only fence: at most two staged rows live
+#pragma unroll
+          for (int c = 0; c <= VMZ; ++c)
+#pragma unroll
+            for (int k = 0; k < CY; ++k) asm volatile("" : "+v"(T[c][k][0]), "+v"(T[c][k][1]) : : "memory");
+        });
+        // input plane `step` feeds outputs m = step - VMZ + c and step - VMZ - c
+        static_for<0, VMZ + 1>([&](auto Cz) __attribute__((always_inline)) {
+          constexpr int c = (int)Cz;
+          constexpr int sp = ((ph - VMZ + c) % NZR + NZR) % NZR;
+#pragma unroll
+          for (int k = 0; k < CY; ++k) {
+            acc[sp][k][0] = acc[sp][k][0] + T[c][k][0];
+            acc[sp][k][1] = acc[sp][k][1] + T[c][k][1];
+          }
+          if constexpr (c > 0) {
+            constexpr int sm = ((ph - VMZ - c) % NZR + NZR) % NZR;
+#pragma unroll
+            for (int k = 0; k < CY; ++k) {
+              acc[sm][k][0] = acc[sm][k][0] + T[c][k][0];
+              acc[sm][k][1] = acc[sm][k][1] + T[c][k][1];
+            }
+          }
+        });
+        // output plane m = step - 2 VMZ is complete
+        constexpr int fs = (ph + 1) % NZR;
+        if (emit) {
+#pragma unroll
+          for (int k = 0; k < CY; ++k) {
+            const int gy = y0 + g * CY + k;
+            if (gy < ny) {
+#pragma unroll
+              for (int q = 0; q < 2; ++q) {
+                if (gx + q < nx) {
+                  const size_t c = ((size_t)gz * ny + gy) * nx + gx + q;
+                  TC out = acc[fs][k][q];
+                  if (src) out = out + sv[k][q];
+                  const TC centre = cv[k][q];
+                  if constexpr (MT::RESID) {
+                    const double r = (double)out - (double)centre;  // R = A X + G - X
+                    xout[c] = (TOUT)r;
+                    if constexpr ((FLAGS & FLAG_REDUCE) != 0) {
+                      const bool ok = __builtin_isfinite(r) && __builtin_isfinite((double)out);
+                      v[NORM_SUM_R2] += ok ? r * r : 0.0;
+                      v[NORM_SUM_PHI2] += ok ? (double)out * (double)out : 0.0;
+                      v[NORM_SUM_PHI] += ok ? (double)out : 0.0;
+                      v[NORM_MAX_DPHI] = ok ? fmax(v[NORM_MAX_DPHI], fabs(r)) : v[NORM_MAX_DPHI];
+                      v[NORM_SUM_DPHI2] += ok ? r * r : 0.0;
+                      v[NORM_BAD] += ok ? 0.0 : 1.0;
+                    }
+                  } else {
+                    xout[c] = (TOUT)out;
+                    if constexpr ((FLAGS & FLAG_REDUCE) != 0) {
+                      const double o = (double)(TOUT)out;
+                      const double d = o - (double)centre;
+                      const bool ok = __builtin_isfinite(o) && __builtin_isfinite(d);
+                      v[NORM_MAX_DPHI] = ok ? fmax(v[NORM_MAX_DPHI], fabs(d)) : v[NORM_MAX_DPHI];
+                      v[NORM_SUM_DPHI2] += ok ? d * d : 0.0;
+                      v[NORM_SUM_PHI2] += ok ? o * o : 0.0;
+                      v[NORM_SUM_PHI] += ok ? o : 0.0;
+                      v[NORM_BAD] += ok ? 0.0 : 1.0;
+                    }
+                  }
+                }
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < CY; ++k) acc[fs][k][0] = acc[fs][k][1] = (TC)0;
+      }
+    });
+  }
+  if constexpr ((FLAGS & FLAG_REDUCE) != 0) block_norms(v, p.partials + (size_t)lin * NUM_NORMS);
+}
+
 template <int LID, int SM, int TILE>
 hipError_t launch_tile3(int flags, StencilParams p, hipStream_t s) {
   constexpr int CY = kStencilCY[TILE], BZ = kStencilBZ[TILE];
-  constexpr bool SEP = kStencilSep[TILE];
-  if constexpr (SEP && !SepPlan3<LID>::t.closed) {
+  constexpr int FORM = kStencilForm[TILE];
+  if constexpr (FORM != STENCIL_BY_VELOCITY && !SepPlan3<LID>::t.closed) {
     return hipErrorInvalidValue;  // not a set of whole shells
   } else {
     constexpr StencilShape sh = stencil_tile_shape(3, TILE);
@@ -499,10 +757,18 @@ hipError_t launch_tile3(int flags, StencilParams p, hipStream_t s) {
     p.gby = (p.ny + sh.ty - 1) / sh.ty;
     const unsigned gbz = (p.nz + sh.tz - 1) / sh.tz;
     const dim3 grid(p.gbx * p.gby * gbz);
-    if (flags & FLAG_REDUCE)
-      hipLaunchKernelGGL((k_stencil3<LID, SM, FLAG_REDUCE, CY, BZ, SEP>), grid, dim3(256), 0, s, p);
-    else
-      hipLaunchKernelGGL((k_stencil3<LID, SM, 0, CY, BZ, SEP>), grid, dim3(256), 0, s, p);
+    if constexpr (FORM == STENCIL_PLANE_SUM) {
+      if (flags & FLAG_REDUCE)
+        hipLaunchKernelGGL((k_stencil3p<LID, SM, FLAG_REDUCE, CY, BZ>), grid, dim3(256), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_stencil3p<LID, SM, 0, CY, BZ>), grid, dim3(256), 0, s, p);
+    } else {
+      constexpr bool SEP = FORM == STENCIL_SEPARABLE;
+      if (flags & FLAG_REDUCE)
+        hipLaunchKernelGGL((k_stencil3<LID, SM, FLAG_REDUCE, CY, BZ, SEP>), grid, dim3(256), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_stencil3<LID, SM, 0, CY, BZ, SEP>), grid, dim3(256), 0, s, p);
+    }
     return hipGetLastError();
   }
 }
@@ -511,7 +777,7 @@ template <int LID, int SM>
 hipError_t launch_smode(int flags, const StencilParams &p, hipStream_t s) {
   constexpr int DIM = Lattice<LID>::DIM;
   if constexpr (DIM == 3) {
-    static_assert(kStencilTiles3 == 10, "one case per tile variant");
+    static_assert(kStencilTiles3 == 16, "one case per tile variant");
     switch (p.tile) {
       case 0: return launch_tile3<LID, SM, 0>(flags, p, s);
       case 1: return launch_tile3<LID, SM, 1>(flags, p, s);
@@ -523,6 +789,12 @@ hipError_t launch_smode(int flags, const StencilParams &p, hipStream_t s) {
       case 7: return launch_tile3<LID, SM, 7>(flags, p, s);
       case 8: return launch_tile3<LID, SM, 8>(flags, p, s);
       case 9: return launch_tile3<LID, SM, 9>(flags, p, s);
+      case 10: return launch_tile3<LID, SM, 10>(flags, p, s);
+      case 11: return launch_tile3<LID, SM, 11>(flags, p, s);
+      case 12: return launch_tile3<LID, SM, 12>(flags, p, s);
+      case 13: return launch_tile3<LID, SM, 13>(flags, p, s);
+      case 14: return launch_tile3<LID, SM, 14>(flags, p, s);
+      case 15: return launch_tile3<LID, SM, 15>(flags, p, s);
     }
     return hipErrorInvalidValue;
   } else {

@@ -6,6 +6,7 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "stencil.hpp"
 #include "lattices.hpp"
 
 namespace lkp {

@@ -55,7 +55,7 @@ def test_stencil_form_equals_population_sweep(lattice):
 
 @pytest.mark.parametrize("lattice", ["D3Q111", "D3Q107"])
 def test_stencil3_every_tile_and_block_order_same_bits(lattice):
-    """Within each family (velocity by velocity; separable), every 3D tile
+    """Within each family (velocity by velocity; separable; plane sums), every 3D tile
     variant and block order the runtime chooses between gives bitwise the same
     sweeps (each output cell accumulates in the same order), on a ragged grid,
     FP64 and FP32, and both families match the oracle.  The reduced norms
@@ -64,7 +64,7 @@ def test_stencil3_every_tile_and_block_order_same_bits(lattice):
     shape = (37, 45, 150)
     s = _src(shape, 11)
     for precision, bar in (("f64", 1e-13), ("f32", 5e-6)):
-      for family in (range(0, 6), range(6, 10)):
+      for family in (range(0, 6), range(6, 10), range(10, 16)):
         out = []
         for tile in family:
             for remap in (0, 4, 16):
