@@ -130,12 +130,13 @@ def oracle_fixed_point(lattice, order, s, tau_lb=None, knudsen=None):
 
 
 def timed_solve(lkp, torch, s, lattice, order, precision, tol, ref=None, check_every=100,
-                chunk=0, label="", **kw) -> dict:
+                chunk=0, label="", max_seconds=0.0, **kw) -> dict:
     """Solve to estimated rel-L2 `tol`; wall time, sweeps, the solver's own
     estimate and, with `ref`, the true error against the oracle's fixed point.
     chunk > 0: consecutive lkp_solve calls of at most `chunk` sweeps (a resumed
     call keeps the convergence history, a stopped refinement its partial
-    correction), one progress line each."""
+    correction), one progress line each; max_seconds > 0 then also caps the
+    wall time (the report says whether the tolerance was reached)."""
     with lkp.Problem(s, lattice, order, precision=precision, **kw) as q:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -147,13 +148,15 @@ def timed_solve(lkp, torch, s, lattice, order, precision, tol, ref=None, check_e
             outer = rep["outer"] if precision in ("f64", "f32") else outer + rep["outer"]
             if chunk <= 0 or rep["status"] == 0 or sweeps >= 4_000_000:
                 break
+            if max_seconds > 0 and time.perf_counter() - t1 > max_seconds:
+                break
             say(f"{label} {precision}: {sweeps} sweeps {time.perf_counter() - t1:.0f} s "
                 f"est {rep['est_rel_err']:.3e}")
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         out = {"precision": precision, "tol_rel_l2": tol, "seconds": round(el, 4),
                "sweeps": sweeps, "outer": outer, "status": rep["status"],
-               "est_rel_err": rep["est_rel_err"]}
+               "converged": rep["status"] == 0, "est_rel_err": rep["est_rel_err"]}
         if ref is not None:
             out["true_rel_l2"] = true_rel_l2(q.phi_host(), ref)
     return out
@@ -514,7 +517,7 @@ def configs_matrix(lkp, torch, W) -> dict:
     """The 1024^2 workload at every order and Knudsen number, FP64 and FP32 +
     refinement, to rel-L2 1e-6 with true errors; the 256^3 problem (tau_lb = 1)
     solved by population sweeps, FP32 + refinement and the BF16 deviation
-    ablation as a separate run."""
+    ablation as a separate run (each capped at 4 minutes of wall time)."""
     s = W.poisson_source("blobs2d", (1024, 1024), seed=12345)
     rows = []
     for N, lat in ORDERS.items():
@@ -531,8 +534,8 @@ def configs_matrix(lkp, torch, W) -> dict:
     abl = []
     for prec in ("bf16dev_ir", "f32_ir"):
         r = timed_solve(lkp, torch, s3, "D3Q111", 5, prec, 1e-6, ref=ref3, check_every=200,
-                        chunk=2000, label="[configs] 256^3 population sweep", tau_lb=1.0,
-                        population_sweep=True)
+                        chunk=2000, label="[configs] 256^3 population sweep", max_seconds=240.0,
+                        tau_lb=1.0, population_sweep=True)
         say(f"[configs] 256^3 population sweep {prec}: {r['seconds']} s, true {r['true_rel_l2']:.2e}")
         abl.append(r)
     return {"c2_1024x1024": rows, "c3_256cubed_population_sweep": abl}
