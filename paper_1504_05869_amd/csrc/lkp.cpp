@@ -276,7 +276,7 @@ SweepParams ir_inner_params(lkp_handle *h, int P) {
   return p;
 }
 
-lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep);
+lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep, bool truncated = false);
 
 lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
                           const lkp_solve_opts &o, lkp_solve_report *rep) {
@@ -312,10 +312,10 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
 }
 
 // x += d - phi_i mean(d), FP64 (scalar state: x += d - mean(d)); next: residual.
-// Also used when max_sweeps ends an inner solve early: the partial correction
-// (a truncated sum of the contraction's powers applied to r) still lowers the
-// error, and a later solve resumes from the updated x.
-lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep) {
+// Also used when max_sweeps ends an inner solve early (truncated): the partial
+// correction (a truncated sum of the contraction's powers applied to r) still
+// lowers the error, and a later solve resumes from the updated x.
+lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep, bool truncated) {
   IrState &s = h->ir;
   const int q = h->scalar ? 1 : h->Q;
   const size_t QN = (size_t)q * h->ncells;
@@ -337,7 +337,18 @@ lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep) {
   s.outer += 1;
   s.first = false;
   h->x_nonzero = true;
-  s.corr_prev = s.corr;
+  // The next residual's estimate is this correction scaled by the residual's
+  // shrink.  After K sweeps at contraction rho the partial correction is about
+  // (1 - rho^K) of the full one, so a truncated correction stands for
+  // |d| / (1 - rho^K); with no rate measured yet it gives no estimate.
+  if (!truncated) {
+    s.corr_prev = s.corr;
+  } else if (s.rate > 0 && s.rate < 1 && s.t_in > 0) {
+    const double got = 1.0 - std::pow(s.rate, (double)s.t_in);
+    s.corr_prev = got > 0 ? s.corr / got : -1.0;
+  } else {
+    s.corr_prev = -1.0;
+  }
   s.rnorm_prev = s.rnorm;
   s.phase = IR_RESID;
   rep->outer = s.outer;
@@ -1224,7 +1235,7 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
       }
       if (h->total_sweeps - start >= o->max_sweeps) {
         if (h->ir.phase == IR_INNER && h->ir.t_in > 0)  // keep the inner work done so far
-          if (lkp_status st = ir_apply_correction(h, &rep)) return st;
+          if (lkp_status st = ir_apply_correction(h, &rep, true)) return st;
         result = fail(LKP_ERR_NOT_CONVERGED, "refinement: max_sweeps reached");
         break;
       }

@@ -614,8 +614,10 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
               if constexpr (CENTRE) cv[k][q] = (TC)xin[c];
             }
           }
-        __syncthreads();
+        // the next plane's loads go out before the barrier: they only write
+        // registers, and the barrier's wait adds to their time to arrive
         if (step + PD < NSTEPS) fetch(std::integral_constant<int, pi>{}, step + PD);
+        __syncthreads();
 
         TC T[VMZ + 1][CY][2];
 #pragma unroll

@@ -30,6 +30,7 @@ class Request:
     knudsen: float
     seed: int
     kind: str               # workloads.poisson_source recipe
+    deadline: float | None = None   # seconds after arrival; past it the request is cancelled
 
 
 @dataclass
@@ -124,11 +125,15 @@ class GpuBackend:
 
     def retire(self, p):
         phi = p.phi_host() if self.keep_phi else None
+        self.cancel(p)
+        return phi
+
+    def cancel(self, p):
+        """Take a problem out of its group and free its device state."""
         for g in self.groups.values():
             if p._h.value in g._members:
                 g.remove(p)
         p.close()
-        return phi
 
     def close(self):
         for g in self.groups.values():
@@ -137,7 +142,9 @@ class GpuBackend:
 
 
 class Server:
-    """Admission by footprint, batched ticks, retirement at tolerance."""
+    """Admission by footprint, batched ticks, retirement at tolerance;
+    requests past their deadline are cancelled (queued ones before admission,
+    resident ones after the tick that passes it) and their memory freed."""
 
     def __init__(self, backend, hbm_budget: int, sweeps_per_tick: int = 50, tol: float = 1e-6,
                  max_sweeps: int = 2_000_000, clock=time.perf_counter, sleep=time.sleep,
@@ -160,11 +167,20 @@ class Server:
         used = 0
         nxt = 0
         t0 = self.clock()
+        cancel = getattr(self.backend, "cancel", self.backend.retire)
+
+        def expired(req, t):
+            return req.deadline is not None and t >= req.arrival + req.deadline
+
         while nxt < len(reqs) or queue or resident:
             now = self.clock() - t0
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 queue.append(reqs[nxt])
                 nxt += 1
+            for req in [q for q in queue if expired(q, now)]:
+                queue.remove(req)
+                results[req.rid].status = "cancelled: deadline expired before admission"
+                results[req.rid].finished = now
             # FIFO admission while the footprint fits the budget
             while queue:
                 req = queue[0]
@@ -188,7 +204,20 @@ class Server:
                 continue
             self.ticks += 1
             for p, rep in self.backend.tick(self.K):
-                if rep["state"] == "running" or p not in resident:
+                if p not in resident:
+                    continue
+                if rep["state"] == "running":
+                    req, fp = resident[p]
+                    now = self.clock() - t0
+                    if expired(req, now):
+                        resident.pop(p)
+                        cancel(p)
+                        used -= fp
+                        res = results[req.rid]
+                        res.sweeps, res.outer = rep["sweeps"], rep["outer"]
+                        res.est_rel_err = rep["est_rel_err"]
+                        res.status = "cancelled: deadline expired"
+                        res.finished = now
                     continue
                 req, fp = resident.pop(p)
                 res = results[req.rid]

@@ -319,6 +319,30 @@ def test_refinement_resumes_from_current_state(precision):
     assert a["sweeps"] + b["sweeps"] <= 1.5 * one["sweeps"] + 200
 
 
+@pytest.mark.parametrize("precision", ["f32_ir", "bf16dev_ir"])
+def test_chunked_refinement_stops_within_twice_tol(precision):
+    """A refinement run as many short calls (each cut by max_sweeps inside an
+    inner solve) stops on an estimate that accounts for the truncated
+    corrections: the answer is within 2x the tolerance of the exact fixed
+    point (a truncated correction taken as complete had it 3x off)."""
+    s = _blobs((64, 48), seed=9)
+    tau = OL.tau_from_knudsen(0.01, OL.get("D2Q81"), 48)   # rho about 0.996 per sweep
+    ref = SP.fixed_point("D2Q81", 5, tau, s)
+    tol = 1e-6
+    with lkp.Problem(s, "D2Q81", 5, knudsen=0.01, precision=precision) as p:
+        total, calls = 0, 0
+        while True:   # 150-sweep calls: each correction about half of the full one
+            rep = p.solve(tol_rel_l2=tol, check_every=50, max_sweeps=150, raise_on_error=False)
+            total += rep["sweeps"]
+            calls += 1
+            if rep["status"] == 0 or total > 2_000_000:
+                break
+        phi = p.phi_host()
+    err = rel_l2(phi, ref)
+    say("chunked", precision, "calls", calls, "sweeps", total, "est", rep["est_rel_err"], "true", err)
+    assert rep["status"] == 0 and calls > 3
+    assert err <= 2 * tol
+
 
 def _sampled_fixed_point_residual(phi, s, lattice, order, tau, ncells=4096, seed=7):
     """Relative residual of the tau_lb = 1 fixed-point equation

@@ -234,6 +234,50 @@ def test_server_end_to_end_small_stream():
     assert summ["peak_hbm_bytes"] <= 2 << 30
 
 
+def test_server_deadline_cancels_resident_request():
+    """A request whose deadline passes while it runs is cancelled after that
+    tick: it leaves its group, its device state is freed, and the other
+    requests of the group still converge to the fixed point."""
+    import dataclasses
+
+    class TickClock:                  # time advances 10 ms per tick, nothing else
+        t = 0.0
+
+        def __call__(self):
+            return self.t
+
+        def sleep(self, dt):
+            self.t += max(dt, 0.0)
+
+    clock = TickClock()
+
+    class Backend(serve.GpuBackend):
+        def tick(self, sweeps):
+            out = super().tick(sweeps)
+            clock.t += 0.01
+            return out
+
+    reqs = serve.make_stream(4, rate=1000.0, seed=5, sizes2d=((48, 48), (64, 64)), sizes3d=())
+    # 15 ms after its arrival: two or three ticks of 20 sweeps, far from converged
+    reqs[1] = dataclasses.replace(reqs[1], deadline=0.015)
+    be = Backend("f32_ir", keep_phi=True)
+    srv = serve.Server(be, hbm_budget=2 << 30, sweeps_per_tick=20, tol=1e-7, clock=clock,
+                       sleep=clock.sleep)
+    res, summ = srv.run(reqs)
+    by = {r.rid: r for r in res}
+    say("deadline", [(r.rid, r.status, r.sweeps) for r in res])
+    assert by[reqs[1].rid].status == "cancelled: deadline expired"
+    assert by[reqs[1].rid].phi is None and summ["completed"] == 3
+    assert all(len(g) == 0 for g in be.groups.values())
+    for q in reqs:
+        if q.rid == reqs[1].rid:
+            continue
+        s = W.poisson_source(q.kind, q.shape, seed=q.seed)
+        tau = OL.tau_from_knudsen(q.knudsen, OL.get(q.lattice), min(q.shape))
+        assert rel_l2(by[q.rid].phi, SP.fixed_point(q.lattice, q.order, tau, s)) <= 2e-7
+    be.close()
+
+
 @pytest.mark.parametrize("precision", ["f32_ir", "f64"])
 def test_group_split_tuned_answers_unchanged(precision):
     """A group with enough work times its batched splits and keeps one (cached

@@ -32,6 +32,7 @@ class ScriptedBackend:
         self.cells_per_tick = cells_per_tick
         self.resident = {}
         self.admitted_order = []
+        self.cancelled = []
         self.max_resident_bytes = 0
 
     def footprint(self, req):
@@ -59,6 +60,10 @@ class ScriptedBackend:
     def retire(self, key):
         del self.resident[key]
         return None
+
+    def cancel(self, key):
+        self.cancelled.append(self.resident[key][0].rid)
+        del self.resident[key]
 
 
 def _run(requests, budget, **kw):
@@ -136,3 +141,24 @@ def test_summary_fields():
     assert abs(s["p50_latency_s"] - 50.5) < 1e-9
     assert abs(s["p99_latency_s"] - 99.01) < 1e-9
     assert abs(s["problems_per_s"] - 1.0) < 1e-12
+
+
+def test_deadline_expiry_cancels_and_frees():
+    """A resident request past its deadline is cancelled after the tick that
+    passes it and its memory goes to the next request; a queued request whose
+    deadline passes while it waits for memory is cancelled unadmitted."""
+    fp = 512 * 512 * 100
+    reqs = [Request(0, 0.0, (512, 512), "D2Q81", 5, 0.1, 0, "blobs2d", deadline=0.015),
+            Request(1, 0.0, (256, 256), "D2Q81", 5, 0.1, 1, "blobs2d", deadline=0.005),
+            Request(2, 0.0, (64, 64), "D2Q81", 5, 0.1, 2, "blobs2d")]
+    be, srv, res, summ = _run(reqs, budget=fp)
+    # request 0 needs 7 ticks of 0.01 s: cancelled after the second, at t = 0.02
+    assert res[0].status == "cancelled: deadline expired" and be.cancelled == [0]
+    assert 0.015 <= res[0].finished <= 0.02 + 1e-12
+    # request 1 waited for memory past its deadline: never admitted
+    assert res[1].status.startswith("cancelled: deadline expired before admission")
+    assert 1 not in be.admitted_order
+    # request 2 took the freed memory and converged
+    assert res[2].status == "converged" and res[2].admitted >= res[0].finished
+    assert not be.resident and srv.peak_used <= fp
+    assert summ["completed"] == 1
