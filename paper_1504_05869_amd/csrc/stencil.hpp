@@ -45,15 +45,19 @@ struct StencilShape {
 //   6..9   separable: sums over +-x offsets first (shared through LDS), then
 //          over +-y, then weights per (x, y, z) offset magnitude, less than
 //          half the arithmetic (sets of whole shells);
-//   10..15 plane sums: a thread owns two adjacent x cells, forms the x sums
+//   10..19 plane sums: a thread owns two adjacent x cells, forms the x sums
 //          in registers from 2-element LDS reads, and accumulates one sum per
 //          |z offset| per input plane (sets of whole shells); the block tile
-//          is 64 x 8 CY instead of 64 x 4 CY.
+//          is 64 x 8 CY instead of 64 x 4 CY.  10..15 stage each plane
+//          through registers one plane ahead; 16..19 load NB planes straight
+//          into LDS (kStencilNB; nx a multiple of 16 bytes' elements).
 enum StencilForm : int { STENCIL_BY_VELOCITY = 0, STENCIL_SEPARABLE = 1, STENCIL_PLANE_SUM = 2 };
-constexpr int kStencilTiles3 = 16;
-constexpr int kStencilCY[kStencilTiles3] = {2, 2, 2, 4, 4, 1, 2, 2, 1, 4, 1, 1, 2, 2, 2, 1};
-constexpr int kStencilBZ[kStencilTiles3] = {32, 16, 8, 16, 8, 16, 32, 16, 16, 16, 16, 32, 64, 16, 32, 64};
-constexpr int kStencilForm[kStencilTiles3] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2};
+constexpr int kStencilTiles3 = 20;
+constexpr int kStencilCY[kStencilTiles3] = {2, 2, 2, 4, 4, 1, 2, 2, 1, 4, 1, 1, 2, 2, 2, 1, 2, 2, 1, 1};
+constexpr int kStencilBZ[kStencilTiles3] = {32, 16, 8, 16, 8, 16, 32, 16, 16, 16,
+                                            16, 32, 64, 16, 32, 64, 32, 64, 32, 64};
+constexpr int kStencilForm[kStencilTiles3] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+constexpr int kStencilNB[kStencilTiles3] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 3, 3, 3, 3};
 // Variant of grids too small to time (the plane-sum form's smallest tile).
 constexpr int kStencilDefault3 = 10;
 constexpr StencilShape stencil_tile_shape(int dim, int tile) {

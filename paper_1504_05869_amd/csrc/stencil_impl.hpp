@@ -505,6 +505,129 @@ struct alignas(2 * sizeof(T)) Pair2 {
   T a, b;
 };
 
+// The plane sums of one staged input plane for a thread's two adjacent x
+// cells on CY rows: T[c][k][q] = sum_{a,b} w[a,b,c] S_b^y S_a^x Phi at output
+// row k, cell q (rows in y order, then a in order).  `row0` points at the
+// staged value x0 + 2 ip - VMX - XS of the thread's first row (row r of the
+// staged plane at row0 + r PITCH); XS = 1 when the rows were staged from one
+// cell further left (an even x origin), so that the 2-element reads stay
+// aligned.  Rows are read one ahead: the reads of row r + 1 are in flight
+// while row r's multiply-adds run.
+template <int LID, int SM, int CY, int PITCH, int XS, class TIN, class TC>
+__device__ __forceinline__ void plane_sums(const TIN *row0, const StencilParams &p,
+                                           TC (&T)[Lattice<LID>::VMZ + 1][CY][2]) {
+  using SP = SepPlan3<LID>;
+  using L = Lattice<LID>;
+  constexpr int VMX = L::VMX, VMY = L::VMY, VMZ = L::VMZ;
+  constexpr int SEG = 2 + 2 * VMX;      // values around a cell pair
+  constexpr int NP = (SEG + XS + 1) / 2;  // 2-element reads per row
+  constexpr int NR = CY + 2 * VMY;      // staged rows a thread reads
+#pragma unroll
+  for (int c = 0; c <= VMZ; ++c)
+#pragma unroll
+    for (int k = 0; k < CY; ++k) T[c][k][0] = T[c][k][1] = (TC)0;
+  TIN seg[2][2 * NP];
+  auto read_row = [&](auto Rc) __attribute__((always_inline)) {
+    constexpr int r = (int)Rc;
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      const Pair2<TIN> q = *reinterpret_cast<const Pair2<TIN> *>(row0 + r * PITCH + 2 * e);
+      seg[r & 1][2 * e] = q.a;
+      seg[r & 1][2 * e + 1] = q.b;
+    }
+  };
+  read_row(std::integral_constant<int, 0>{});
+  static_for<0, NR>([&](auto R) __attribute__((always_inline)) {
+    constexpr int r = (int)R;
+    if constexpr (r + 1 < NR) read_row(std::integral_constant<int, r + 1>{});
+    // x sums of the two cells: X[a][q] = S_a^x Phi at cell q
+    TC X[VMX + 1][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      X[0][q] = (TC)seg[r & 1][XS + VMX + q];
+#pragma unroll
+      for (int a = 1; a <= VMX; ++a)
+        X[a][q] = (TC)seg[r & 1][XS + VMX + q + a] + (TC)seg[r & 1][XS + VMX + q - a];
+    }
+    static_for<0, CY>([&](auto K) __attribute__((always_inline)) {
+      constexpr int k = (int)K;
+      constexpr int dy = r - VMY - k;  // y offset of this row for output row k
+      constexpr int b = dy < 0 ? -dy : dy;
+      if constexpr (b <= VMY) {
+        static_for<0, VMZ + 1>([&](auto Cz) __attribute__((always_inline)) {
+          constexpr int c = (int)Cz;
+          static_for<0, VMX + 1>([&](auto A) __attribute__((always_inline)) {
+            constexpr int a = (int)A;
+            constexpr int o = SP::t.orb[a][b][c];
+            if constexpr (o >= 0) {
+              TC w;
+              if constexpr (sizeof(TC) == 8) w = (TC)p.coef.d[o];
+              else w = (TC)p.coef.f[o];
+              T[c][k][0] = FmaT<SM>::f(w, X[a][0], T[c][k][0]);
+              T[c][k][1] = FmaT<SM>::f(w, X[a][1], T[c][k][1]);
+            }
+          });
+        });
+      }
+    });
+    // compiler-only fence: at most two staged rows live
+#pragma unroll
+    for (int c = 0; c <= VMZ; ++c)
+#pragma unroll
+      for (int k = 0; k < CY; ++k) asm volatile("" : "+v"(T[c][k][0]), "+v"(T[c][k][1]) : : "memory");
+  });
+}
+
+// Store a thread's finished output cells (two adjacent x cells on CY rows of
+// plane gz): Phi' = acc + src, or R = acc + src - centre in SMODE_RESID, and
+// on check sweeps add their norms to v.
+template <int SM, int FLAGS, int CY, class TC, class TOUT>
+__device__ __forceinline__ void emit_rows(const TC (&acc)[CY][2], const TC (&sv)[CY][2],
+                                          const TC (&cv)[CY][2], bool has_src, TOUT *xout, int gz,
+                                          int gy0, int gx, int nx, int ny, double (&v)[NUM_NORMS]) {
+  using MT = SModeTraits<SM>;
+#pragma unroll
+  for (int k = 0; k < CY; ++k) {
+    const int gy = gy0 + k;
+    if (gy < ny) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (gx + q < nx) {
+          const size_t c = ((size_t)gz * ny + gy) * nx + gx + q;
+          TC out = acc[k][q];
+          if (has_src) out = out + sv[k][q];
+          const TC centre = cv[k][q];
+          if constexpr (MT::RESID) {
+            const double r = (double)out - (double)centre;  // R = A X + G - X
+            xout[c] = (TOUT)r;
+            if constexpr ((FLAGS & FLAG_REDUCE) != 0) {
+              const bool ok = __builtin_isfinite(r) && __builtin_isfinite((double)out);
+              v[NORM_SUM_R2] += ok ? r * r : 0.0;
+              v[NORM_SUM_PHI2] += ok ? (double)out * (double)out : 0.0;
+              v[NORM_SUM_PHI] += ok ? (double)out : 0.0;
+              v[NORM_MAX_DPHI] = ok ? fmax(v[NORM_MAX_DPHI], fabs(r)) : v[NORM_MAX_DPHI];
+              v[NORM_SUM_DPHI2] += ok ? r * r : 0.0;
+              v[NORM_BAD] += ok ? 0.0 : 1.0;
+            }
+          } else {
+            xout[c] = (TOUT)out;
+            if constexpr ((FLAGS & FLAG_REDUCE) != 0) {
+              const double o = (double)(TOUT)out;
+              const double d = o - (double)centre;
+              const bool ok = __builtin_isfinite(o) && __builtin_isfinite(d);
+              v[NORM_MAX_DPHI] = ok ? fmax(v[NORM_MAX_DPHI], fabs(d)) : v[NORM_MAX_DPHI];
+              v[NORM_SUM_DPHI2] += ok ? d * d : 0.0;
+              v[NORM_SUM_PHI2] += ok ? o * o : 0.0;
+              v[NORM_SUM_PHI] += ok ? o : 0.0;
+              v[NORM_BAD] += ok ? 0.0 : 1.0;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Plane-sum form of the 3D stencil for sets of whole shells.  With
 // S_d f(x) = f(x + d) + f(x - d) (S_0 f = f) the stencil is
 //   Phi'(z) = sum_c S_c^z T_c,   T_c = sum_{a,b} w[a,b,c] S_b^y S_a^x Phi,
@@ -536,8 +659,6 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
   constexpr int LX = TX + 2 * VMX, LY = TY + 2 * VMY, NL = LX * LY;
   constexpr int NST = (NL + 255) / 256;
   constexpr int NSTEPS = BZ + 2 * VMZ;
-  constexpr int SEG = 2 + 2 * VMX;  // staged values around a cell pair
-  constexpr int NR = CY + 2 * VMY;  // staged rows a thread reads
   constexpr bool CENTRE = MT::RESID || (FLAGS & FLAG_REDUCE) != 0;
   static_assert(SP::t.closed, "the plane-sum form needs a set of whole shells");
   static_assert(LX % 2 == 0 && NL % 2 == 0, "2-element LDS reads need even rows");
@@ -620,63 +741,7 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
         __syncthreads();
 
         TC T[VMZ + 1][CY][2];
-#pragma unroll
-        for (int c = 0; c <= VMZ; ++c)
-#pragma unroll
-          for (int k = 0; k < CY; ++k) T[c][k][0] = T[c][k][1] = (TC)0;
-        // rows are read one ahead: the reads of row r + 1 are in flight
-        // while row r's multiply-adds run
-        const TIN *rowbase = t + g * CY * LX + 2 * ip;
-        TIN seg[2][SEG];
-        auto read_row = [&](auto Rc) __attribute__((always_inline)) {
-          constexpr int r = (int)Rc;
-#pragma unroll
-          for (int e = 0; e < SEG; e += 2) {
-            const Pair2<TIN> q = *reinterpret_cast<const Pair2<TIN> *>(rowbase + r * LX + e);
-            seg[r & 1][e] = q.a;
-            seg[r & 1][e + 1] = q.b;
-          }
-        };
-        read_row(std::integral_constant<int, 0>{});
-        static_for<0, NR>([&](auto R) __attribute__((always_inline)) {
-          constexpr int r = (int)R;
-          if constexpr (r + 1 < NR) read_row(std::integral_constant<int, r + 1>{});
-          // x sums of the two cells: X[a][q] = S_a^x Phi at cell q
-          TC X[VMX + 1][2];
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            X[0][q] = (TC)seg[r & 1][VMX + q];
-#pragma unroll
-            for (int a = 1; a <= VMX; ++a)
-              X[a][q] = (TC)seg[r & 1][VMX + q + a] + (TC)seg[r & 1][VMX + q - a];
-          }
-          static_for<0, CY>([&](auto K) __attribute__((always_inline)) {
-            constexpr int k = (int)K;
-            constexpr int dy = r - VMY - k;  // y offset of this row for output row k
-            constexpr int b = dy < 0 ? -dy : dy;
-            if constexpr (b <= VMY) {
-              static_for<0, VMZ + 1>([&](auto Cz) __attribute__((always_inline)) {
-                constexpr int c = (int)Cz;
-                static_for<0, VMX + 1>([&](auto A) __attribute__((always_inline)) {
-                  constexpr int a = (int)A;
-                  constexpr int o = SP::t.orb[a][b][c];
-                  if constexpr (o >= 0) {
-                    TC w;
-                    if constexpr (sizeof(TC) == 8) w = (TC)p.coef.d[o];
-                    else w = (TC)p.coef.f[o];
-                    T[c][k][0] = FmaT<SM>::f(w, X[a][0], T[c][k][0]);
-                    T[c][k][1] = FmaT<SM>::f(w, X[a][1], T[c][k][1]);
-                  }
-                });
-              });
-            }
-          });
-          // compiler-only fence: at most two staged rows live
-#pragma unroll
-          for (int c = 0; c <= VMZ; ++c)
-#pragma unroll
-            for (int k = 0; k < CY; ++k) asm volatile("" : "+v"(T[c][k][0]), "+v"(T[c][k][1]) : : "memory");
-        });
+        plane_sums<LID, SM, CY, LX, 0>(t + g * CY * LX + 2 * ip, p, T);
         // input plane `step` feeds outputs m = step - VMZ + c and step - VMZ - c
         static_for<0, VMZ + 1>([&](auto Cz) __attribute__((always_inline)) {
           constexpr int c = (int)Cz;
@@ -697,53 +762,254 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
         });
         // output plane m = step - 2 VMZ is complete
         constexpr int fs = (ph + 1) % NZR;
-        if (emit) {
-#pragma unroll
-          for (int k = 0; k < CY; ++k) {
-            const int gy = y0 + g * CY + k;
-            if (gy < ny) {
-#pragma unroll
-              for (int q = 0; q < 2; ++q) {
-                if (gx + q < nx) {
-                  const size_t c = ((size_t)gz * ny + gy) * nx + gx + q;
-                  TC out = acc[fs][k][q];
-                  if (src) out = out + sv[k][q];
-                  const TC centre = cv[k][q];
-                  if constexpr (MT::RESID) {
-                    const double r = (double)out - (double)centre;  // R = A X + G - X
-                    xout[c] = (TOUT)r;
-                    if constexpr ((FLAGS & FLAG_REDUCE) != 0) {
-                      const bool ok = __builtin_isfinite(r) && __builtin_isfinite((double)out);
-                      v[NORM_SUM_R2] += ok ? r * r : 0.0;
-                      v[NORM_SUM_PHI2] += ok ? (double)out * (double)out : 0.0;
-                      v[NORM_SUM_PHI] += ok ? (double)out : 0.0;
-                      v[NORM_MAX_DPHI] = ok ? fmax(v[NORM_MAX_DPHI], fabs(r)) : v[NORM_MAX_DPHI];
-                      v[NORM_SUM_DPHI2] += ok ? r * r : 0.0;
-                      v[NORM_BAD] += ok ? 0.0 : 1.0;
-                    }
-                  } else {
-                    xout[c] = (TOUT)out;
-                    if constexpr ((FLAGS & FLAG_REDUCE) != 0) {
-                      const double o = (double)(TOUT)out;
-                      const double d = o - (double)centre;
-                      const bool ok = __builtin_isfinite(o) && __builtin_isfinite(d);
-                      v[NORM_MAX_DPHI] = ok ? fmax(v[NORM_MAX_DPHI], fabs(d)) : v[NORM_MAX_DPHI];
-                      v[NORM_SUM_DPHI2] += ok ? d * d : 0.0;
-                      v[NORM_SUM_PHI2] += ok ? o * o : 0.0;
-                      v[NORM_SUM_PHI] += ok ? o : 0.0;
-                      v[NORM_BAD] += ok ? 0.0 : 1.0;
-                    }
-                  }
-                }
-              }
-            }
-          }
-        }
+        if (emit)
+          emit_rows<SM, FLAGS, CY>(acc[fs], sv, cv, src != nullptr, xout, gz, y0 + g * CY, gx, nx, ny,
+                                   v);
 #pragma unroll
         for (int k = 0; k < CY; ++k) acc[fs][k][0] = acc[fs][k][1] = (TC)0;
       }
     });
   }
+  if constexpr ((FLAGS & FLAG_REDUCE) != 0) block_norms(v, p.partials + (size_t)lin * NUM_NORMS);
+}
+
+// s_waitcnt that waits until at most N vector-memory operations of this wave
+// are in flight (lgkm and exp counters left alone); wait_vm_n takes N at run
+// time (wave-uniform, at most NMAX).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+template <int NMAX>
+__device__ __forceinline__ void wait_vm_n(int n) {
+  bool done = false;
+  static_for<0, NMAX + 1>([&](auto I) __attribute__((always_inline)) {
+    if (!done && n == (int)I) {
+      wait_vm<(int)I>();
+      done = true;
+    }
+  });
+  if (!done) wait_vm<0>();
+}
+
+// Requests of one block for a field of T: NU 16-byte units per lane-slot
+// table, every lane issuing the same NR = ceil(NU / 256) direct
+// global-to-LDS loads (lanes past the last unit repeat it into the buffer's
+// tail), so that every wave has the same number of loads in flight.
+template <class T, int NU>
+struct LdsRows {
+  static constexpr int E = 16 / (int)sizeof(T);  // elements per unit
+  static constexpr int NR = (NU + 255) / 256;    // loads per lane
+  static constexpr int SLOT = NR * 256 * E;      // elements per buffer
+  unsigned off[NR];                              // element offset within a plane
+  __device__ __forceinline__ void request(const T *plane, T *buf, int wv) const {
+    using LdsPtr = __attribute__((address_space(3))) void *;
+    using GlobalPtr = const __attribute__((address_space(1))) void *;
+    T *dst = buf + 64 * wv * E;
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+      __builtin_amdgcn_global_load_lds((GlobalPtr)(plane + off[j]), (LdsPtr)(dst + 256 * j * E), 16, 0,
+                                       0);
+  }
+};
+
+// Plane-sum form with every load a direct global-to-LDS load: NB input planes
+// are in LDS or in flight at once (plane step + NB - 1 is requested while
+// plane step is summed, so a request has NB - 1 steps' work to arrive instead
+// of one), and the source (and centre) rows of each output plane travel the
+// same way, NB - 1 steps ahead of their use.  No register waits on a global
+// load, so the only waits are the ones below: before step t, for plane t and
+// everything requested before it, counting the requests issued after it (a
+// wave's vector-memory operations complete in issue order).  Input rows are
+// staged from the x origin x0 - VXA (VMX rounded up to whole 16-byte units)
+// so that every unit is aligned and none straddles the periodic seam; the
+// variant needs nx to be a multiple of a unit's elements.  A step stores the
+// previous step's outputs before it requests anything, so the stores never
+// enter the count.  The arithmetic is k_stencil3p's (same helpers, same
+// order): the variants of both give the same bits.
+template <int LID, int SM, int FLAGS, int CY, int BZ, int NB>
+__global__ void __launch_bounds__(256) k_stencil3pa(StencilParams p) {
+  using SP = SepPlan3<LID>;
+  using L = Lattice<LID>;
+  using MT = SModeTraits<SM>;
+  using TIN = typename MT::TIN;
+  using TOUT = typename MT::TOUT;
+  using TSRC = typename MT::TSRC;
+  using TC = typename MT::TC;
+  constexpr int VMX = L::VMX, VMY = L::VMY, VMZ = L::VMZ;
+  constexpr int TX = 64, NG = 8, TY = NG * CY;  // 32 cell pairs x 8 row groups
+  constexpr int NZR = 2 * VMZ + 1;
+  constexpr int E = 16 / (int)sizeof(TIN);     // input elements per unit
+  constexpr int ES = 16 / (int)sizeof(TSRC);   // source elements per unit
+  constexpr int VXA = (VMX + E - 1) / E * E;    // x halo in whole units
+  constexpr int PITCH = TX + 2 * VXA;           // staged input row (elements)
+  constexpr int RU = PITCH / E;                 // units per staged input row
+  constexpr int LY = TY + 2 * VMY;
+  constexpr int XS = VXA - VMX;                 // staged cells left of the halo
+  constexpr int NSTEPS = BZ + 2 * VMZ;
+  constexpr bool CENTRE = MT::RESID || (FLAGS & FLAG_REDUCE) != 0;
+  using InRows = LdsRows<TIN, RU * LY>;
+  using SrcRows = LdsRows<TSRC, TX * TY / ES>;
+  using CenRows = LdsRows<TIN, TX * TY / E>;
+  constexpr int NIN = InRows::NR;                                 // loads per input plane
+  constexpr int NOUT = SrcRows::NR + (CENTRE ? CenRows::NR : 0);  // loads per output plane
+  constexpr int KMAX = (NB - 2) * (NIN + NOUT);
+  static_assert(SP::t.closed, "the plane-sum form needs a set of whole shells");
+  static_assert(NB >= 3 && KMAX < 64, "three or more buffers; vmcnt range");
+  static_assert(2 * VMZ >= NB - 1, "no output plane is requested before the loop");
+  __shared__ __align__(16) TIN tile[NB][InRows::SLOT];
+  __shared__ __align__(16) TSRC sbuf[NB][SrcRows::SLOT];
+  __shared__ __align__(16) TIN cbuf[CENTRE ? NB : 1][CENTRE ? CenRows::SLOT : 4];
+
+  const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
+  const unsigned nb = gridDim.x;
+  const unsigned lin = p.remap ? xcd_runs(blockIdx.x, nb, p.remap) : blockIdx.x;
+  const unsigned bxi = lin % p.gbx, byi = (lin / p.gbx) % p.gby, bzi = lin / (p.gbx * p.gby);
+  const int x0 = (int)bxi * TX, y0 = (int)byi * TY, z0 = (int)bzi * BZ;
+  const unsigned pcells = (unsigned)nx * (unsigned)ny;
+  const TIN *__restrict__ xin = reinterpret_cast<const TIN *>(p.xin);
+  // without a source field the source loads read Phi (ignored), so that the
+  // count of loads per step stays the same
+  const TSRC *__restrict__ src = reinterpret_cast<const TSRC *>(p.src ? p.src : p.xin);
+  const bool has_src = p.src != nullptr;
+  TOUT *__restrict__ xout = reinterpret_cast<TOUT *>(p.xout);
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+
+  // input unit u: staged row u / RU, x = x0 - VXA + E (u % RU), rows wrapped
+  InRows in;
+#pragma unroll
+  for (int j = 0; j < NIN; ++j) {
+    const int u = min((int)threadIdx.x + 256 * j, RU * LY - 1);
+    in.off[j] = (unsigned)(pmod(y0 + u / RU - VMY, ny) * nx + pmod(x0 - VXA + E * (u % RU), nx));
+  }
+  // output unit u: row u / (TX / ES) of the tile, x = x0 + ES (u % (TX / ES));
+  // rows and columns past the grid wrap (their values are never used)
+  SrcRows so;
+#pragma unroll
+  for (int j = 0; j < SrcRows::NR; ++j) {
+    const int u = min((int)threadIdx.x + 256 * j, TX * TY / ES - 1);
+    so.off[j] = (unsigned)(pmod(y0 + u / (TX / ES), ny) * nx + pmod(x0 + ES * (u % (TX / ES)), nx));
+  }
+  CenRows co;
+  if constexpr (CENTRE) {
+#pragma unroll
+    for (int j = 0; j < CenRows::NR; ++j) {
+      const int u = min((int)threadIdx.x + 256 * j, TX * TY / E - 1);
+      co.off[j] = (unsigned)(pmod(y0 + u / (TX / E), ny) * nx + pmod(x0 + E * (u % (TX / E)), nx));
+    }
+  }
+  // input plane j (z = z0 - VMZ + j) goes to tile[j % NB]; the source and
+  // centre rows of step t's output plane (z = z0 + t - 2 VMZ) to sbuf[t % NB]
+  auto request_in = [&](int j) __attribute__((always_inline)) {
+    in.request(xin + (size_t)pmod(z0 - VMZ + j, nz) * pcells, tile[j % NB], wv);
+  };
+  auto request_out = [&](int t) __attribute__((always_inline)) {
+    const size_t base = (size_t)pmod(z0 + t - 2 * VMZ, nz) * pcells;
+    so.request(src + base, sbuf[t % NB], wv);
+    if constexpr (CENTRE) co.request(xin + base, cbuf[t % NB], wv);
+  };
+  // output rows of step t are requested with input plane t + 1, in the step
+  // t + 2 - NB, before it: both have landed once plane t + 1 has
+  auto out_requested = [](int t) { return t >= 2 * VMZ && t <= NSTEPS - 1; };
+
+  const int ip = (int)(threadIdx.x % 32);  // cell pair
+  const int g = (int)(threadIdx.x / 32);   // row group
+  const int gx = x0 + 2 * ip;
+  TC acc[NZR][CY][2];
+#pragma unroll
+  for (int j = 0; j < NZR; ++j)
+#pragma unroll
+    for (int k = 0; k < CY; ++k) acc[j][k][0] = acc[j][k][1] = (TC)0;
+  double v[NUM_NORMS] = {0, 0, 0, 0, 0, 0};
+
+  // outputs of step t (ring slot `slot`), their source and centre from LDS
+  auto emit = [&](auto SLOTc, int t) __attribute__((always_inline)) {
+    constexpr int slot = (int)SLOTc;
+    const int m = t - 2 * VMZ;
+    if (m >= 0 && z0 + m < nz) {
+      TC sv[CY][2], cv[CY][2];
+#pragma unroll
+      for (int k = 0; k < CY; ++k) {
+        const int e = (g * CY + k) * TX + 2 * ip;
+        const Pair2<TSRC> q = *reinterpret_cast<const Pair2<TSRC> *>(sbuf[t % NB] + e);
+        sv[k][0] = (TC)q.a;
+        sv[k][1] = (TC)q.b;
+        cv[k][0] = cv[k][1] = (TC)0;
+        if constexpr (CENTRE) {
+          const Pair2<TIN> c = *reinterpret_cast<const Pair2<TIN> *>(cbuf[t % NB] + e);
+          cv[k][0] = (TC)c.a;
+          cv[k][1] = (TC)c.b;
+        }
+      }
+      emit_rows<SM, FLAGS, CY>(acc[slot], sv, cv, has_src, xout, z0 + m, y0 + g * CY, gx, nx, ny, v);
+    }
+#pragma unroll
+    for (int k = 0; k < CY; ++k) acc[slot][k][0] = acc[slot][k][1] = (TC)0;
+  };
+
+  // the last input plane, opaque to the compiler: every request stays behind
+  // a branch, where it does not make the compiler wait for all loads in
+  // flight before the next LDS reads (the explicit waits order them)
+  int last_plane = NSTEPS - 1;
+  asm volatile("" : "+s"(last_plane));
+  static_for<0, NB - 1>([&](auto K) __attribute__((always_inline)) {
+    if ((int)K <= last_plane) request_in((int)K);
+  });
+  for (int s0 = 0; s0 < NSTEPS; s0 += NZR) {
+    static_for<0, NZR>([&](auto PHX) __attribute__((always_inline)) {
+      constexpr int ph = (int)PHX;
+      const int step = s0 + ph;
+      if (step < NSTEPS) {  // block-uniform
+        // plane `step` (and the output rows of step - 1) have landed once
+        // only the loads issued after it are left: steps step + 1 - NB + j,
+        // j = 1 .. NB - 2, issued output rows of step - 1 + j and plane
+        // step + j
+        int later = 0;
+#pragma unroll
+        for (int j = 1; j <= NB - 2; ++j)
+          later += (out_requested(step - 1 + j) ? NOUT : 0) + (step + j <= NSTEPS - 1 ? NIN : 0);
+        wait_vm_n<KMAX>(later);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // outputs finished by the previous step (ring slot ph; none at step 0)
+        emit(std::integral_constant<int, ph>{}, step - 1);
+        // the buffers written next were last read in the previous step,
+        // which every wave has finished (barrier above)
+        if (out_requested(step + NB - 2)) request_out(step + NB - 2);
+        if (step + NB - 1 <= last_plane) request_in(step + NB - 1);
+
+        TC T[VMZ + 1][CY][2];
+        plane_sums<LID, SM, CY, PITCH, XS & 1>(tile[step % NB] + g * CY * PITCH + 2 * ip + (XS & ~1),
+                                               p, T);
+        // input plane `step` feeds outputs m = step - VMZ + c and step - VMZ - c
+        static_for<0, VMZ + 1>([&](auto Cz) __attribute__((always_inline)) {
+          constexpr int c = (int)Cz;
+          constexpr int sp = ((ph - VMZ + c) % NZR + NZR) % NZR;
+#pragma unroll
+          for (int k = 0; k < CY; ++k) {
+            acc[sp][k][0] = acc[sp][k][0] + T[c][k][0];
+            acc[sp][k][1] = acc[sp][k][1] + T[c][k][1];
+          }
+          if constexpr (c > 0) {
+            constexpr int sm = ((ph - VMZ - c) % NZR + NZR) % NZR;
+#pragma unroll
+            for (int k = 0; k < CY; ++k) {
+              acc[sm][k][0] = acc[sm][k][0] + T[c][k][0];
+              acc[sm][k][1] = acc[sm][k][1] + T[c][k][1];
+            }
+          }
+        });
+      }
+    });
+  }
+  // the last step's outputs: their rows were requested with no plane after
+  wait_vm<0>();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  emit(std::integral_constant<int, ((NSTEPS - 1) % NZR + 1) % NZR>{}, NSTEPS - 1);
   if constexpr ((FLAGS & FLAG_REDUCE) != 0) block_norms(v, p.partials + (size_t)lin * NUM_NORMS);
 }
 
@@ -759,7 +1025,16 @@ hipError_t launch_tile3(int flags, StencilParams p, hipStream_t s) {
     p.gby = (p.ny + sh.ty - 1) / sh.ty;
     const unsigned gbz = (p.nz + sh.tz - 1) / sh.tz;
     const dim3 grid(p.gbx * p.gby * gbz);
-    if constexpr (FORM == STENCIL_PLANE_SUM) {
+    constexpr int NB = kStencilNB[TILE];
+    if constexpr (FORM == STENCIL_PLANE_SUM && NB > 0) {
+      // whole 16-byte units per row: nx a multiple of their element count
+      constexpr unsigned E = 16 / sizeof(typename SModeTraits<SM>::TIN);
+      if (p.nx % E != 0) return hipErrorInvalidValue;
+      if (flags & FLAG_REDUCE)
+        hipLaunchKernelGGL((k_stencil3pa<LID, SM, FLAG_REDUCE, CY, BZ, NB>), grid, dim3(256), 0, s, p);
+      else
+        hipLaunchKernelGGL((k_stencil3pa<LID, SM, 0, CY, BZ, NB>), grid, dim3(256), 0, s, p);
+    } else if constexpr (FORM == STENCIL_PLANE_SUM) {
       if (flags & FLAG_REDUCE)
         hipLaunchKernelGGL((k_stencil3p<LID, SM, FLAG_REDUCE, CY, BZ>), grid, dim3(256), 0, s, p);
       else
@@ -779,7 +1054,7 @@ template <int LID, int SM>
 hipError_t launch_smode(int flags, const StencilParams &p, hipStream_t s) {
   constexpr int DIM = Lattice<LID>::DIM;
   if constexpr (DIM == 3) {
-    static_assert(kStencilTiles3 == 16, "one case per tile variant");
+    static_assert(kStencilTiles3 == 20, "one case per tile variant");
     switch (p.tile) {
       case 0: return launch_tile3<LID, SM, 0>(flags, p, s);
       case 1: return launch_tile3<LID, SM, 1>(flags, p, s);
@@ -797,6 +1072,10 @@ hipError_t launch_smode(int flags, const StencilParams &p, hipStream_t s) {
       case 13: return launch_tile3<LID, SM, 13>(flags, p, s);
       case 14: return launch_tile3<LID, SM, 14>(flags, p, s);
       case 15: return launch_tile3<LID, SM, 15>(flags, p, s);
+      case 16: return launch_tile3<LID, SM, 16>(flags, p, s);
+      case 17: return launch_tile3<LID, SM, 17>(flags, p, s);
+      case 18: return launch_tile3<LID, SM, 18>(flags, p, s);
+      case 19: return launch_tile3<LID, SM, 19>(flags, p, s);
     }
     return hipErrorInvalidValue;
   } else {

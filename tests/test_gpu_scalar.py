@@ -61,10 +61,10 @@ def test_stencil3_every_tile_and_block_order_same_bits(lattice):
     FP64 and FP32, and both families match the oracle.  The reduced norms
     group their partial sums by block, so they agree to rounding."""
     import os
-    shape = (37, 45, 150)
+    shape = (37, 45, 148)      # nx a multiple of 4: every plane-sum variant takes it
     s = _src(shape, 11)
     for precision, bar in (("f64", 1e-13), ("f32", 5e-6)):
-      for family in (range(0, 6), range(6, 10), range(10, 16)):
+      for family in (range(0, 6), range(6, 10), range(10, 20)):
         out = []
         for tile in family:
             for remap in (0, 4, 16):
@@ -87,6 +87,25 @@ def test_stencil3_every_tile_and_block_order_same_bits(lattice):
         err = rel_l2(out[0][0], ref)
         say(lattice, precision, "tiles", list(family), "x 3 block orders bitwise equal; vs oracle", err)
         assert err <= bar
+
+
+@pytest.mark.parametrize("lattice", ["D3Q111", "D3Q107"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_stencil3_lds_staged_tiles_refuse_unaligned_rows(lattice, precision):
+    """The plane-sum variants that load whole 16-byte units straight into LDS
+    need nx to be a multiple of a unit's elements (2 in FP64, 4 in FP32): on
+    other grids a forced choice is refused before anything is launched, the
+    tuner passes them over, and the state is left as it was."""
+    import os
+    shape = (9, 12, 70 if precision == "f32" else 71)
+    s = _src(shape, 5)
+    os.environ["LKP_STENCIL_TILE"] = "16"
+    try:
+        with lkp.Problem(s, lattice, 5, tau_lb=1.0, precision=precision) as p:
+            with pytest.raises(lkp.LkpError):
+                p.step(2)
+    finally:
+        os.environ.pop("LKP_STENCIL_TILE", None)
 
 
 @pytest.mark.parametrize("shape", [(37, 40, 150), (32, 16, 64), (5, 33, 70)])
