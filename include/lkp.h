@@ -170,12 +170,24 @@ lkp_status lkp_destroy(lkp_handle *h);
  * that `d` accepts (0 if `d` is invalid; the last error is left as it was). */
 int64_t lkp_footprint_bytes(const lkp_problem_desc *d);
 
+/* The slowest decay the sweep of `d` allows: the largest modulus of the
+ * one-sweep amplification over the grid's modes other than the mass mode
+ * (Fourier analysis of the sweep of Sec. 4 and 5; the stability analysis of
+ * the same modes decides LKP_ERR_UNSTABLE), written to *rho.  It peaks at the
+ * kinetic value |1 - 1/tau_lb|, at a corner mode (every wavevector component
+ * 0 or pi) or at the longest wave along an axis, and those are the modes
+ * taken.  lkp_solve never estimates the distance to the fixed point with a
+ * contraction below it.  Host only (no device call, `source` not read).
+ * Errors: as lkp_create's validation (LKP_ERR_ARG, LKP_ERR_LATTICE_ORDER,
+ * LKP_ERR_UNSTABLE). */
+lkp_status lkp_contraction_bound(const lkp_problem_desc *d, double *rho);
+
 typedef struct lkp_solve_opts {
   double tol_rel_l2;    /* > 0: stop when the estimated relative L2 distance of Phi to the
                            fixed point, |dPhi| rho / (1 - rho) / |Phi| with rho the largest
-                           of the last four per-sweep contractions measured between checks,
-                           is <= tol_rel_l2 (refinement: the last correction scaled by the
-                           residual's shrink since it) */
+                           of the last four per-sweep contractions measured between checks
+                           and of lkp_contraction_bound, is <= tol_rel_l2 (refinement: the
+                           last correction scaled by the residual's shrink since it) */
   double tol_maxchange; /* > 0: stop when max_x |Phi_t - Phi_{t-1}| < tol_maxchange */
   int64_t max_sweeps;   /* hard cap on sweeps done by this call (> 0) */
   int32_t check_every;  /* sweeps between convergence checks (>= 1) */

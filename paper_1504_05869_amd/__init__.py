@@ -19,8 +19,8 @@ import torch
 from . import _lib
 from ._lib import LATTICES, PRECISIONS, LkpError, check
 
-__all__ = ["Problem", "Group", "lattice_info", "footprint_bytes", "LkpError", "LATTICES",
-           "PRECISIONS", "library_path", "solve_opts"]
+__all__ = ["Problem", "Group", "lattice_info", "footprint_bytes", "contraction_bound", "LkpError",
+           "LATTICES", "PRECISIONS", "library_path", "solve_opts"]
 
 
 def library_path() -> str:
@@ -65,6 +65,18 @@ def footprint_bytes(shape, lattice, order, tau_lb=None, knudsen=None, precision=
     d.flags = ((_lib.FLAG_IN_PLACE if in_place else 0)
                | (_lib.FLAG_POPULATION_SWEEP if population_sweep else 0))
     return int(_lib.load().lkp_footprint_bytes(ctypes.byref(d)))
+
+
+def contraction_bound(shape, lattice, order, tau_lb=None, knudsen=None, drift=None) -> float:
+    """Slowest decay the sweep allows on this grid (lkp_contraction_bound)."""
+    d = _desc(shape, lattice, order, tau_lb, knudsen, "f64", False, True)
+    if drift is not None:
+        for a, u in enumerate(drift):
+            d.drift[a] = float(u)
+    rho = ctypes.c_double()
+    check(_lib.load().lkp_contraction_bound(ctypes.byref(d), ctypes.byref(rho)),
+          "lkp_contraction_bound")
+    return float(rho.value)
 
 
 def lattice_info(lattice: str, order: int = 1) -> dict:

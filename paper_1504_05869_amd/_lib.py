@@ -17,7 +17,8 @@ STATUS = {0: "LKP_OK", 1: "LKP_ERR_ARG", 2: "LKP_ERR_LATTICE_ORDER", 3: "LKP_ERR
           4: "LKP_ERR_SOURCE_MEAN", 5: "LKP_ERR_OOM", 6: "LKP_ERR_HIP",
           7: "LKP_ERR_NOT_CONVERGED", 8: "LKP_ERR_DIVERGED", 9: "LKP_ERR_STATE",
           10: "LKP_ERR_UNSUPPORTED"}
-EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_solve", "lkp_step",
+EXPORTS = ["lkp_create", "lkp_destroy", "lkp_footprint_bytes", "lkp_contraction_bound",
+           "lkp_solve", "lkp_step",
            "lkp_residual", "lkp_get_phi", "lkp_get_populations", "lkp_set_populations",
            "lkp_lattice_info", "lkp_get_info", "lkp_get_coefficients", "lkp_set_equilibrium",
            "lkp_sync", "lkp_last_error",
@@ -98,6 +99,7 @@ def load() -> ctypes.CDLL:
         "lkp_create": (ctypes.c_int, [P(ProblemDesc), P(H)]),
         "lkp_destroy": (ctypes.c_int, [H]),
         "lkp_footprint_bytes": (ctypes.c_int64, [P(ProblemDesc)]),
+        "lkp_contraction_bound": (ctypes.c_int, [P(ProblemDesc), P(ctypes.c_double)]),
         "lkp_solve": (ctypes.c_int, [H, P(SolveOpts), P(SolveReport)]),
         "lkp_step": (ctypes.c_int, [H, ctypes.c_int64]),
         "lkp_residual": (ctypes.c_int, [H, P(ResidualReport)]),

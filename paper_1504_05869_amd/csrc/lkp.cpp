@@ -122,6 +122,12 @@ lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
     t.nrates += 1;
     t.rate = 0.0;
     for (int j = 0; j < std::min(t.nrates, Tracker::kRates); ++j) t.rate = std::max(t.rate, t.rates[j]);
+    // A slow mode carries little of the one-sweep change while faster ones
+    // still decay (its share of the change is (1 - lambda) times its share of
+    // the error), so the measured contraction can sit below the slowest
+    // mode's for thousands of sweeps; the estimate never uses less than the
+    // slowest decay the grid's modes allow.
+    if (h->rho_bound < 1.0) t.rate = std::max(t.rate, h->rho_bound);
     rep->rate = t.rate;
   }
   if (l2 > 0) t.min_l2 = std::min(t.min_l2, l2);
@@ -230,8 +236,11 @@ lkp_status ir_after_residual(lkp_handle *h, const double nr[NUM_NORMS], const lk
   rep->outer = s.outer;
   if (nr[NORM_BAD] > 0) return fail(LKP_ERR_DIVERGED, "non-finite residual");
   if (s.corr_prev >= 0 && s.rnorm_prev > 0 && phi_l2 > 0) {
-    // the last correction scaled by how much the residual shrank since it
-    rep->est_rel_err = s.corr_prev * (s.rnorm / s.rnorm_prev) / phi_l2;
+    // the last correction scaled by how much the residual shrank since it,
+    // and never less than what that correction's inner solve estimated it
+    // left undone (the residual shrinks faster than the error when the error
+    // left is in slow modes)
+    rep->est_rel_err = std::max(s.corr_prev * (s.rnorm / s.rnorm_prev), s.left) / phi_l2;
     s.est = rep->est_rel_err;
     if (rep->est_rel_err <= o.tol_rel_l2) *converged = true;
   }
@@ -259,6 +268,7 @@ void ir_reset(lkp_handle *h) {
     // the last correction and the residual before it: the first residual of
     // the resumed solve already gives an error estimate
     h->ir.corr_prev = old.corr_prev;
+    h->ir.left = old.left;
     h->ir.rnorm_prev = old.rnorm_prev;
     h->ir.est = old.est;
   }
@@ -297,17 +307,23 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
   s.best_l2 = std::min(s.best_l2, l2);
   s.l2_prev = l2;
   s.t_prev = s.t_in;
-  rep->rate = s.rate;
-  const double est = (s.rate > 0 && s.rate < 1) ? l2 * s.rate / (1 - s.rate) : 1e300;
+  // the contraction of the correction's error: the measured one, never below
+  // the slowest decay the grid's modes allow (as for the plain sweep)
+  const double rho = (s.rate > 0 && h->rho_bound < 1) ? std::max(s.rate, h->rho_bound) : s.rate;
+  rep->rate = rho;
+  const double est = (rho > 0 && rho < 1) ? l2 * rho / (1 - rho) : 1e300;
   // FP32 sweeps cannot bring the correction closer than about u32 / (1 - rho)
   // of its size (rounding of each sweep, amplified by the slow contraction);
   // stop there rather than sweep on without gaining accuracy.  BF16 deviation
   // storage has no such simple floor (its rounding is relative to the
   // deviation, not the population): there the stall rule decides.
-  const double floor32 =
-      (!h->bf16dev() && s.rate > 0 && s.rate < 1) ? 2.0 * 5.96e-8 / (1 - s.rate) : 0.0;
+  const double floor32 = (!h->bf16dev() && rho > 0 && rho < 1) ? 2.0 * 5.96e-8 / (1 - rho) : 0.0;
   const double goal = std::max(s.inner_tol, floor32);
-  if (!(s.corr == 0 || est <= goal * s.corr || s.stall >= 2)) return LKP_OK;
+  const bool met = s.corr == 0 || est <= goal * s.corr;
+  if (!(met || s.stall >= 2)) return LKP_OK;
+  // what the correction leaves undone, by its own estimate; a solve stopped
+  // for stalling has no meaningful one (its change is rounding noise)
+  s.left = s.corr == 0 ? 0.0 : (met ? std::max(est, floor32 * s.corr) : -1.0);
   return ir_apply_correction(h, rep);
 }
 
@@ -341,13 +357,16 @@ lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep, bool trunca
   // shrink.  After K sweeps at contraction rho the partial correction is about
   // (1 - rho^K) of the full one, so a truncated correction stands for
   // |d| / (1 - rho^K); with no rate measured yet it gives no estimate.
+  const double rho = (s.rate > 0 && h->rho_bound < 1) ? std::max(s.rate, h->rho_bound) : s.rate;
   if (!truncated) {
     s.corr_prev = s.corr;
-  } else if (s.rate > 0 && s.rate < 1 && s.t_in > 0) {
-    const double got = 1.0 - std::pow(s.rate, (double)s.t_in);
+  } else if (rho > 0 && rho < 1 && s.t_in > 0) {
+    const double got = 1.0 - std::pow(rho, (double)s.t_in);
     s.corr_prev = got > 0 ? s.corr / got : -1.0;
+    s.left = got > 0 ? s.corr_prev - s.corr : -1.0;
   } else {
     s.corr_prev = -1.0;
+    s.left = -1.0;
   }
   s.rnorm_prev = s.rnorm;
   s.phase = IR_RESID;
@@ -747,10 +766,12 @@ StencilParams stencil_params(const lkp_handle *h) {
 // Pick the 3D stencil's tile variant and block order by timing each
 // candidate on the handle's own buffers (a few sweeps from the current Phi
 // into the idle buffer: the state is unchanged).  The variants of one family
-// (velocity by velocity, or separable) give the same bits; the two families
-// differ by rounding.  Cached per process and (set, mode, size class);
-// LKP_STENCIL_TILE / LKP_STENCIL_REMAP force a choice, LKP_AUTOTUNE=0 keeps
-// the default (the velocity-by-velocity tile 0).
+// (velocity by velocity, separable, or plane sums) give the same bits; the
+// families differ by rounding.  A variant a grid does not take (the
+// LDS-staged plane sums on rows of a ragged 16-byte length) is refused before
+// it launches and passed over.  Cached per process and (set, mode, size
+// class); LKP_STENCIL_TILE / LKP_STENCIL_REMAP force a choice, LKP_AUTOTUNE=0
+// and grids below 2^18 cells keep the default (the smallest plane-sum tile).
 lkp_status tune_stencil(lkp_handle *h) {
   if (h->dim != 3) return LKP_OK;
   h->stile = kStencilDefault3;
@@ -951,6 +972,7 @@ lkp_status init_handle(const lkp_problem_desc *d, lkp_handle *h) {
     h->phi[i] = (double)phi[i];
     h->chi[i] = (double)chi[i];
   }
+  h->rho_bound = contraction_bound(lc.table, h->dim, h->phi.data(), h->omega, h->n);
   h->simple_wrap = h->n[0] >= max_component(lc.table, 0) && h->n[1] >= max_component(lc.table, 1) &&
                    h->n[2] >= max_component(lc.table, 2);
   // omega = 1 exactly: run the scalar stencil form unless populations are asked
@@ -1107,6 +1129,15 @@ void pull_to_swapped(const lkp_handle *h, const std::vector<double> &in, std::ve
 extern "C" {
 
 const char *lkp_last_error(void) { return lkp::rt::last_error(); }
+
+lkp_status lkp_contraction_bound(const lkp_problem_desc *d, double *rho) {
+  if (!rho) return fail(LKP_ERR_ARG, "null output pointer");
+  lkp_handle h;
+  if (lkp_status st = init_handle(d, &h)) return st;
+  *rho = h.rho_bound;
+  clear_error();
+  return LKP_OK;
+}
 
 int64_t lkp_footprint_bytes(const lkp_problem_desc *d) {
   const std::string keep = lkp::rt::last_error();

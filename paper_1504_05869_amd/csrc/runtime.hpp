@@ -56,6 +56,7 @@ struct IrState {
   int outer = 0;
   double rnorm = -1.0, rnorm_prev = -1.0;
   double corr = 0.0, corr_prev = -1.0;
+  double left = -1.0;         // the last correction's own estimate of its remaining error (Phi norm)
   double est = 1.0;           // estimated relative error of x (1 for x = 0)
   double inner_tol = 1e-4;    // relative accuracy the current inner solve aims at
   int dc = 0;                 // current inner correction buffer
@@ -72,6 +73,7 @@ struct lkp_handle {
   int64_t n[3] = {1, 1, 1};
   unsigned ncells = 0;
   double tau_lb = 0, omega = 0, cs2 = 0;
+  double rho_bound = 0;      // slowest decay the grid's modes allow (rt::contraction_bound)
   std::vector<double> w, phi, chi;
   bool drift = false;       // advection-diffusion handle (nonzero drift in phi_i)
   std::vector<double> c64;  // [omega phi_i]_Q, [chi_i]_Q (FP64 sweeps, residual)

@@ -3,9 +3,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 namespace lkp {
 namespace rt {
@@ -79,6 +81,67 @@ lkp_status validate_desc(const lkp_problem_desc *d, LatticeConstants *lc, double
 
 bool has_drift(const lkp_problem_desc *d) {
   return d->drift[0] != 0.0 || d->drift[1] != 0.0 || d->drift[2] != 0.0;
+}
+
+double contraction_bound(const VelTable &T, int dim, const double *phi, double omega,
+                         const int64_t n[3]) {
+  using C = std::complex<double>;
+  const int Q = T.q;
+  const double a = 1.0 - omega;
+  double best = std::fabs(a);
+  // Corner modes: e_j = +1 or -1 by the parity of v_j's components along the
+  // axes where k = pi.  With A, B the sums of phi_j over e_j = +1 and -1, the
+  // eigenvalues other than +-a solve
+  //   lambda^2 - omega (A - B) lambda - (a^2 + omega a (A + B)) = 0.
+  for (int mask = 1; mask < (1 << dim); ++mask) {
+    bool exists = true;
+    for (int ax = 0; ax < dim; ++ax)
+      if (((mask >> ax) & 1) && n[ax] < 2) exists = false;
+    if (!exists) continue;
+    double A = 0.0, B = 0.0;
+    for (int j = 0; j < Q; ++j) {
+      int par = 0;
+      for (int ax = 0; ax < dim; ++ax)
+        if ((mask >> ax) & 1) par += T.v[j][ax];
+      if (par & 1) B += phi[j];
+      else A += phi[j];
+    }
+    const double b = omega * (A - B);
+    const C r = std::sqrt(C(b * b + 4.0 * (a * a + omega * a * (A + B)), 0.0));
+    best = std::max({best, std::abs((b + r) / 2.0), std::abs((b - r) / 2.0)});
+  }
+  // The longest wave along each axis: the root of
+  //   f(lambda) = 1 + omega sum_j phi_j e_j / (a e_j - lambda) = 0
+  // that continues lambda = 1 of the mass mode, by Newton's method from 1.
+  // Where that root is not isolated (kinetic regime, where the corners and
+  // |1 - omega| dominate) Newton does not settle and the axis is skipped.
+  const double kPi = 3.14159265358979323846;
+  for (int ax = 0; ax < dim; ++ax) {
+    if (n[ax] < 2) continue;
+    const double k = 2.0 * kPi / (double)n[ax];
+    std::vector<C> e(Q);
+    for (int j = 0; j < Q; ++j) e[j] = std::polar(1.0, -k * (double)T.v[j][ax]);
+    C lam(1.0, 0.0);
+    bool settled = false;
+    for (int it = 0; it < 100; ++it) {
+      C f(1.0, 0.0), fp(0.0, 0.0);
+      for (int j = 0; j < Q; ++j) {
+        const C den = a * e[j] - lam;
+        const C t = omega * phi[j] * e[j] / den;
+        f += t;
+        fp += t / den;
+      }
+      const C step = f / fp;
+      if (!std::isfinite(step.real()) || !std::isfinite(step.imag())) break;
+      lam -= step;
+      if (std::abs(step) < 1e-14) {
+        settled = true;
+        break;
+      }
+    }
+    if (settled) best = std::max(best, std::abs(lam));
+  }
+  return best;
 }
 
 }  // namespace rt

@@ -22,5 +22,18 @@ lkp_status validate_desc(const lkp_problem_desc *d, LatticeConstants *lc, double
 // Whether the description asks for the drifted (advection-diffusion) equilibrium.
 bool has_drift(const lkp_problem_desc *d);
 
+// The slowest decay the sweep allows on a periodic grid of n[0..dim-1] cells:
+// the largest modulus of its one-sweep amplification over the grid's modes
+// other than the mass mode (Fourier analysis of the sweep, Sec. 4 and 5: mode
+// k maps the post-collision populations by (1 - omega) E + omega phi e^T,
+// E = diag(e), e_j = exp(-i k.v_j)).  Taken over the modes where it peaks:
+// the kinetic value |1 - omega| (the k = 0 modes other than mass), every
+// corner mode (each component of k 0 or pi; a closed form, since e_j = +-1),
+// and the longest wave along each axis (the root of the secular equation
+// that continues the mass eigenvalue 1, by Newton's method).  phi: the Q
+// equilibrium shape values.
+double contraction_bound(const VelTable &T, int dim, const double *phi, double omega,
+                         const int64_t n[3]);
+
 }  // namespace rt
 }  // namespace lkp

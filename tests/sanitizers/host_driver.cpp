@@ -2,6 +2,7 @@
 // host compiler, no GPU): the library's constant solves and the validation of
 // problem descriptions, including malformed ones.  Exit status 0 and "OK" on
 // success; any sanitizer report aborts the run.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -121,6 +122,23 @@ int main() {
     EXPECT(rt::validate_desc(&d, &lc, &tau) == LKP_OK);
   }
   EXPECT(rt::validate_desc(nullptr, &lc, &tau) == LKP_ERR_ARG);
+  // the contraction bound of every set and order: a modulus in (0, 1] at a
+  // stable tau_lb, on grids with odd, even and unit sides
+  for (int id = 0; id < LKP_NUM_LATTICES; ++id) {
+    LatticeConstants c;
+    EXPECT(lattice_constants(id, &c));
+    for (int order : {1, 3, 5, 7}) {
+      std::vector<long double> phl, chl;
+      if (!shape_coefficients(c, order, &phl, &chl)) continue;
+      std::vector<double> ph(phl.begin(), phl.end());
+      const double t = std::max(1.3, stability_threshold(id, order) + 0.05);
+      for (int64_t side : {1, 7, 16}) {
+        const int64_t n[3] = {side, c.table.dim > 1 ? side + 1 : 1, c.table.dim > 2 ? side : 1};
+        const double rho = rt::contraction_bound(c.table, c.table.dim, ph.data(), 1.0 / t, n);
+        EXPECT(std::isfinite(rho) && rho > 0.0 && rho <= 1.0 + 1e-12);
+      }
+    }
+  }
   // an over-long message is truncated, not overrun
   std::vector<char> big(4000, 'x');
   big.back() = 0;

@@ -233,3 +233,66 @@ def test_new_entry_points_reject_null_arguments():
     assert _lib.STATUS[lib.lkp_set_equilibrium(None, buf.ctypes.data, 0)] == "LKP_ERR_ARG"
     c = ctypes.c_int64()
     assert _lib.STATUS[lib.lkp_group_graph_stats(None, ctypes.byref(c), None)] == "LKP_ERR_ARG"
+
+
+def _largest_mode(lattice, order, tau_lb, shape, u=None):
+    """Largest |eigenvalue| of the sweep's amplification over every mode of a
+    periodic grid except the mass mode (numpy eigenvalues of the Q x Q mode
+    matrices, with the oracle's coefficients)."""
+    import itertools
+    from oracle import drift as OD
+    lat = OL.get(lattice)
+    phi = OL.coefficients(lat, order)[0] if u is None else OD.coefficients(lat, order, u)[0]
+    V = lat.v3()[:, :lat.dim].astype(float)[:, ::-1]       # numpy axis order (z, y, x)
+    om = 1.0 / tau_lb
+    best = 0.0
+    for k in itertools.product(*[2 * np.pi * np.arange(n) / n for n in shape]):
+        k = np.array(k)
+        if not k.any():
+            continue
+        e = np.exp(-1j * (V @ k))
+        M = (1 - om) * np.diag(e) + om * np.outer(phi, e)
+        best = max(best, float(np.max(np.abs(np.linalg.eigvals(M)))))
+    return best
+
+
+@pytest.mark.parametrize("lattice,order,shape,taus", [
+    ("D2Q81", 5, (10, 12), (0.65, 1.0, 3.0, 50.0)),
+    ("D2Q25", 3, (12, 9), (0.6, 1.0, 20.0)),
+    ("D2Q169", 7, (14, 14), (0.85, 1.0, 9.0)),
+    ("D2Q5", 1, (15, 16), (0.6, 1.0, 5.0)),
+    ("D1Q13", 7, (40,), (0.85, 1.0, 40.0)),
+    ("D2Q37", 5, (12, 10), (0.7, 2.0)),
+    ("D3Q111", 5, (8, 6, 6), (0.7, 1.0, 10.0, 184.0)),
+    ("D3Q107", 5, (6, 6, 6), (0.7, 3.0)),
+])
+def test_contraction_bound_is_the_slowest_mode(lattice, order, shape, taus):
+    """lkp_contraction_bound equals the largest amplification over every mode
+    of the grid (mass mode aside), found here by brute force: the modes it
+    takes (|1 - omega|, the corner modes, the longest wave per axis) are where
+    the maximum sits, across sets, orders, relaxation times and odd and even
+    sides."""
+    for tau in taus:
+        want = _largest_mode(lattice, order, tau, shape)
+        got = lkp.contraction_bound(shape, lattice, order, tau_lb=tau)
+        assert abs(got - want) <= 1e-9, (lattice, tau, got, want)
+
+
+def test_contraction_bound_with_drift_and_at_the_headline_size():
+    """A drifted equilibrium (advection-diffusion) keeps the bound the largest
+    mode on a small grid; at 512^3 D3Q111 Kn = 0.3 the slowest mode is the
+    checkerboard (pi, pi, pi), which decays by 0.99947 per sweep, slower than
+    the kinetic 1 - 1/tau_lb = 0.99458 and the longest wave's 0.99634."""
+    u = (0.05, 0.02)
+    for tau in (0.8, 4.0):
+        want = _largest_mode("D2Q81", 5, tau, (10, 12), u=u)
+        got = lkp.contraction_bound((10, 12), "D2Q81", 5, tau_lb=tau, drift=u)
+        assert abs(got - want) <= 1e-9, (tau, got, want)
+    lat = OL.get("D3Q111")
+    phi = OL.coefficients(lat, 5)[0]
+    tau = OL.tau_from_knudsen(0.3, lat, 512)
+    om = 1.0 / tau
+    e = (-1.0) ** lat.v3().sum(axis=1)
+    cb = np.max(np.abs(np.linalg.eigvals((1 - om) * np.diag(e) + om * np.outer(phi, e))))
+    got = lkp.contraction_bound((512, 512, 512), "D3Q111", 5, knudsen=0.3)
+    assert abs(got - cb) <= 1e-12 and abs(got - 0.99947500) < 1e-7

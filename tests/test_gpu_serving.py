@@ -314,3 +314,53 @@ def test_group_split_tuned_answers_unchanged(precision):
         g.close()
         for p in probs:
             p.close()
+
+
+def test_solve_after_group_membership_uses_its_own_split():
+    """A problem solved with captured chunk graphs, then stepped in a group at
+    another velocity split, then removed and solved again: the second solve
+    runs at the problem's own split again (its chunk graphs are keyed by the
+    split), so its norms and answer equal an eager twin's bit for bit."""
+    shape, kn, seed = (96, 112), 0.2, 41
+    s = _source(shape, seed)
+    pa = lkp.Problem(s, "D2Q81", 5, knudsen=kn)
+    pb = lkp.Problem(s, "D2Q81", 5, knudsen=kn)
+    ga = gb = None
+    keys = ("sweeps", "l2_change", "max_change", "phi_l2", "est_rel_err")
+    try:
+        os.environ["LKP_SPLIT"] = "1"      # the split is fixed at the first sweep
+        try:
+            pa.solve(tol_rel_l2=1e-300, max_sweeps=40, check_every=20, use_graph=True,
+                     raise_on_error=False)
+            pb.solve(tol_rel_l2=1e-300, max_sweeps=40, check_every=20, use_graph=False,
+                     raise_on_error=False)
+        finally:
+            os.environ.pop("LKP_SPLIT", None)
+        assert pa.info()["velocity_groups"] == 1
+        os.environ["LKP_SPLIT"] = "2"      # a group's split is fixed at its creation
+        try:
+            ga, gb = lkp.Group("D2Q81", 5, "f64"), lkp.Group("D2Q81", 5, "f64")
+        finally:
+            os.environ.pop("LKP_SPLIT", None)
+        ga.add(pa, tol_rel_l2=1e-300)
+        gb.add(pb, tol_rel_l2=1e-300)
+        for g in (ga, gb):
+            g.step(20)
+            assert g.split() == 2
+        ga.remove(pa)
+        gb.remove(pb)
+        assert pa.info()["velocity_groups"] == 1
+        ra = pa.solve(tol_rel_l2=1e-300, max_sweeps=60, check_every=20, use_graph=True,
+                      raise_on_error=False)
+        rb = pb.solve(tol_rel_l2=1e-300, max_sweeps=60, check_every=20, use_graph=False,
+                      raise_on_error=False)
+        say("after group", {k: ra[k] for k in keys})
+        for k in keys:
+            assert ra[k] == rb[k] or (np.isnan(ra[k]) and np.isnan(rb[k])), (k, ra[k], rb[k])
+        assert np.array_equal(pa.phi_host(), pb.phi_host())
+    finally:
+        for g in (ga, gb):
+            if g is not None:
+                g.close()
+        pa.close()
+        pb.close()
