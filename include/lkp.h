@@ -184,10 +184,14 @@ lkp_status lkp_contraction_bound(const lkp_problem_desc *d, double *rho);
 
 typedef struct lkp_solve_opts {
   double tol_rel_l2;    /* > 0: stop when the estimated relative L2 distance of Phi to the
-                           fixed point, |dPhi| rho / (1 - rho) / |Phi| with rho the largest
-                           of the last four per-sweep contractions measured between checks
-                           and of lkp_contraction_bound, is <= tol_rel_l2 (refinement: the
-                           last correction scaled by the residual's shrink since it) */
+                           fixed point, |D| rho^m / (1 - rho^m) / |Phi|, is <= tol_rel_l2.
+                           D: the change of Phi over the last m sweeps (with tol_rel_l2
+                           alone, a population solve compares with the Phi stored before
+                           each chunk, m = the chunk; otherwise m = 1); rho: the largest of
+                           the last four per-sweep contractions measured between checks and
+                           of lkp_contraction_bound (refinement: the last correction scaled
+                           by the residual's shrink since it, and at least what its inner
+                           solve estimated it left) */
   double tol_maxchange; /* > 0: stop when max_x |Phi_t - Phi_{t-1}| < tol_maxchange */
   int64_t max_sweeps;   /* hard cap on sweeps done by this call (> 0) */
   int32_t check_every;  /* sweeps between convergence checks (>= 1) */
@@ -203,8 +207,10 @@ typedef struct lkp_solve_report {
   int64_t total_sweeps;  /* sweeps since creation */
   int32_t outer;         /* refinement steps (F32_IR) */
   int32_t status;        /* same as the return value */
-  double max_change;     /* max |Phi_t - Phi_{t-1}| at the last check */
-  double l2_change;      /* ||Phi_t - Phi_{t-1}||_2 at the last check */
+  double max_change;     /* max |Phi_t - Phi_s| at the last check: s = t - 1, or, for a
+                            population solve with tol_rel_l2 alone, the sweep of the Phi
+                            stored before the check's chunk (the change over the chunk) */
+  double l2_change;      /* ||Phi_t - Phi_s||_2 at the last check (s as above) */
   double phi_l2;         /* ||Phi||_2 */
   double mass;           /* sum_x Phi */
   double est_rel_err;    /* estimated relative L2 distance to the fixed point */

@@ -247,15 +247,24 @@ void set_failed(lkp_handle *h, lkp_status st) {
   h->grep.status = st;
 }
 
-// K plain sweeps (F64 / F32) of every member, norms on the last two.
+// K plain sweeps (F64 / F32) of every member; the last sweep reduces each
+// member's norms against the Phi of the sweep before it (pair: members with
+// a max-change tolerance) or against its Phi stored before the step (the
+// change over the whole step), exactly as lkp_solve would for that member.
 lkp_status step_plain(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
+  std::vector<char> pair(run.size());
+  bool any_pair = false;
+  for (size_t k = 0; k < run.size(); ++k) {
+    pair[k] = !interval_checks(run[k], run[k]->gopts);
+    any_pair = any_pair || pair[k];
+  }
   auto enqueue = [&](const Sink &out) -> lkp_status {
     std::vector<int> cur(run.size());
     for (size_t k = 0; k < run.size(); ++k) cur[k] = run[k]->cur;
     std::vector<Slot> slots(run.size());
     for (int j = 0; j < K; ++j) {
       int flags = 0;
-      if (j == K - 2) flags = FLAG_PHI;
+      if (j == K - 2 && any_pair) flags = FLAG_PHI;
       if (j == K - 1) flags = FLAG_REDUCE;
       for (size_t k = 0; k < run.size(); ++k) {
         lkp_handle *h = run[k];
@@ -264,25 +273,48 @@ lkp_status step_plain(lkp_group *g, int K, std::vector<lkp_handle *> &run) {
         s.fin = h->f[cur[k]];
         s.fout = h->f[1 - cur[k]];
         s.src = h->S;
+        // both kinds compare with phib[0] and write phib[1]: pair members
+        // after the sweep before stored phib[0], interval members against the
+        // previous check's Phi there (a FLAG_PHI sweep before, if any member
+        // needs one, writes their phib[1], which the last sweep overwrites)
         s.phi_prev = flags == FLAG_REDUCE ? h->phib[0] : nullptr;
-        s.phi_out = flags == FLAG_PHI ? h->phib[0] : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
+        s.phi_out = flags == FLAG_PHI ? h->phib[pair[k] ? 0 : 1]
+                                      : (flags == FLAG_REDUCE ? h->phib[1] : nullptr);
         cur[k] = 1 - cur[k];
       }
       if (lkp_status st = launch_batched(g, g->mode(), flags, slots, out)) return st;
     }
     for (size_t k = 0; k < run.size(); ++k)
       if (lkp_status st = finish_slot(g, run[k], k, out)) return st;
+    // interval members keep this step's Phi in phib[0] for the next check
+    for (size_t k = 0; k < run.size(); ++k) {
+      if (pair[k]) continue;
+      lkp_handle *h = run[k];
+      if (out.sig) {
+        const void *args[2] = {h->phib[1], h->phib[0]};
+        out.record(args, sizeof args);
+        out.record(&h->ncells, sizeof h->ncells);
+      } else {
+        LKP_HIP_TRY(launch_copy_f64(h->phib[1], h->phib[0], h->ncells, out.stream));
+      }
+    }
     return LKP_OK;
   };
+  // sweeps between the two Phi each member's change compares (0: none valid)
+  std::vector<int64_t> span(run.size());
+  for (size_t k = 0; k < run.size(); ++k) {
+    const lkp_handle *h = run[k];
+    if (pair[k]) span[k] = h->total_sweeps + K >= 2 ? 1 : 0;
+    else span[k] = h->phi_sweep[0] >= 0 ? h->total_sweeps + K - h->phi_sweep[0] : 0;
+  }
   if (lkp_status st = run_tick(g, enqueue)) return st;
   if (lkp_status st = read_slots(g, run.size())) return st;
   for (size_t k = 0; k < run.size(); ++k) {
     lkp_handle *h = run[k];
-    commit_chunk(h, K);
+    commit_chunk(h, K, pair[k] != 0);
     h->g_sweeps += K;
     bool conv = false;
-    const bool prev_ok = h->total_sweeps >= 2;
-    lkp_status st = track_check(h, g->norms_host + k * NUM_NORMS, prev_ok, h->gopts, &h->grep, &conv);
+    lkp_status st = track_check(h, g->norms_host + k * NUM_NORMS, span[k], h->gopts, &h->grep, &conv);
     if (st != LKP_OK) {
       set_failed(h, st);
     } else if (conv) {

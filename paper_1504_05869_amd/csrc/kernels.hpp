@@ -157,6 +157,8 @@ hipError_t launch_equilibrium(const double *phi0, const EqCoef &coef, void *out,
                               int q, hipStream_t s);
 hipError_t launch_f32_to_f64(const float *in, double *out, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+// dst = src, n doubles (a kernel, so that a captured graph holds no copy node)
+hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
 // partials[NUM_NORMS * blocks] (blocks <= max_blocks, the buffer's capacity):
 // slot NORM_SUM_PHI gets the sum of d over all n values, taken in the pull

@@ -90,10 +90,19 @@ lkp_status finish_norms(lkp_handle *h, unsigned nblocks, double *dst_dev, hipStr
   return LKP_OK;
 }
 
-void commit_chunk(lkp_handle *h, int k) {
+bool interval_checks(const lkp_handle *h, const lkp_solve_opts &o) {
+  return !h->scalar && !(o.tol_maxchange > 0) && o.tol_rel_l2 > 0;
+}
+
+void commit_chunk(lkp_handle *h, int k, bool pair) {
   const int64_t t0 = h->total_sweeps;
   if (k % 2) h->cur = 1 - h->cur;
-  if (k >= 2) {
+  if (!pair) {
+    // the change over the chunk: Phi_t written to phib[1] and copied to
+    // phib[0], where the next check compares with it
+    h->phi_last = 1;
+    h->phi_sweep[0] = h->phi_sweep[1] = t0 + k;
+  } else if (k >= 2) {
     h->phi_sweep[0] = t0 + k - 1;
     h->phi_sweep[1] = t0 + k;
     h->phi_last = 1;
@@ -104,7 +113,7 @@ void commit_chunk(lkp_handle *h, int k) {
   h->total_sweeps = t0 + k;
 }
 
-lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
+lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], int64_t span,
                        const lkp_solve_opts &o, lkp_solve_report *rep, bool *converged) {
   *converged = false;
   Tracker &t = h->trk;
@@ -114,9 +123,11 @@ lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
   rep->l2_change = std::sqrt(nr[NORM_SUM_DPHI2]);
   rep->phi_l2 = std::sqrt(nr[NORM_SUM_PHI2]);
   rep->mass = nr[NORM_SUM_PHI];
-  if (!prev_ok) return LKP_OK;
+  if (span < 1) return LKP_OK;
   const double l2 = rep->l2_change;
-  if (t.l2_prev > 0 && l2 > 0 && h->total_sweeps > t.t_prev) {
+  // changes over windows of equal length shrink by the contraction to the
+  // power of the sweeps between them
+  if (t.l2_prev > 0 && l2 > 0 && h->total_sweeps > t.t_prev && span == t.span_prev) {
     t.rates[t.nrates % Tracker::kRates] =
         std::pow(l2 / t.l2_prev, 1.0 / (double)(h->total_sweeps - t.t_prev));
     t.nrates += 1;
@@ -139,7 +150,10 @@ lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
       rep->est_rel_err = 0;
       *converged = true;
     } else if (t.rate > 0 && t.rate < 1 && rep->phi_l2 > 0) {
-      rep->est_rel_err = l2 * t.rate / (1 - t.rate) / rep->phi_l2;
+      // a change D over the last `span` sweeps of a geometric decay at rate r
+      // leaves D r^span / (1 - r^span) to go (span = 1: d r / (1 - r))
+      const double rs = std::pow(t.rate, (double)span);
+      rep->est_rel_err = l2 * rs / (1 - rs) / rep->phi_l2;
       if (rep->est_rel_err <= o.tol_rel_l2) *converged = true;
     } else {
       rep->est_rel_err = INFINITY;
@@ -147,6 +161,7 @@ lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
   }
   t.l2_prev = l2;
   t.t_prev = h->total_sweeps;
+  t.span_prev = span;
   return LKP_OK;
 }
 
@@ -208,6 +223,7 @@ lkp_status ir_begin_inner(lkp_handle *h, const lkp_solve_opts &o) {
     LKP_HIP_TRY(launch_fill_f32(h->d32[0], 0.0f, QN, h->stream));
   }
   s.dc = 0;
+  s.est_in = -1.0;
   // Inner accuracy: as asked, or just enough to close the remaining gap
   // (30 % margin), never below the FP32 sweep's own floor (~1e-7 relative).
   if (o.ir_inner_tol > 0) {
@@ -312,12 +328,15 @@ lkp_status ir_after_inner(lkp_handle *h, const double nr[NUM_NORMS], int K,
   const double rho = (s.rate > 0 && h->rho_bound < 1) ? std::max(s.rate, h->rho_bound) : s.rate;
   rep->rate = rho;
   const double est = (rho > 0 && rho < 1) ? l2 * rho / (1 - rho) : 1e300;
+  s.est_in = est < 1e300 ? est : -1.0;
   // FP32 sweeps cannot bring the correction closer than about u32 / (1 - rho)
-  // of its size (rounding of each sweep, amplified by the slow contraction);
-  // stop there rather than sweep on without gaining accuracy.  BF16 deviation
-  // storage has no such simple floor (its rounding is relative to the
-  // deviation, not the population): there the stall rule decides.
-  const double floor32 = (!h->bf16dev() && rho > 0 && rho < 1) ? 2.0 * 5.96e-8 / (1 - rho) : 0.0;
+  // of its size (rounding of each sweep, amplified by the contraction the
+  // solve shows); stop there rather than sweep on without gaining accuracy.
+  // BF16 deviation storage has no such simple floor (its rounding is
+  // relative to the deviation, not the population): there the stall rule
+  // decides.
+  const double floor32 =
+      (!h->bf16dev() && s.rate > 0 && s.rate < 1) ? 2.0 * 5.96e-8 / (1 - s.rate) : 0.0;
   const double goal = std::max(s.inner_tol, floor32);
   const bool met = s.corr == 0 || est <= goal * s.corr;
   if (!(met || s.stall >= 2)) return LKP_OK;
@@ -357,13 +376,14 @@ lkp_status ir_apply_correction(lkp_handle *h, lkp_solve_report *rep, bool trunca
   // shrink.  After K sweeps at contraction rho the partial correction is about
   // (1 - rho^K) of the full one, so a truncated correction stands for
   // |d| / (1 - rho^K); with no rate measured yet it gives no estimate.
-  const double rho = (s.rate > 0 && h->rho_bound < 1) ? std::max(s.rate, h->rho_bound) : s.rate;
+  // What a truncated correction leaves undone is its inner solve's latest
+  // estimate (which never uses less than the slowest decay the grid allows).
   if (!truncated) {
     s.corr_prev = s.corr;
-  } else if (rho > 0 && rho < 1 && s.t_in > 0) {
-    const double got = 1.0 - std::pow(rho, (double)s.t_in);
+  } else if (s.rate > 0 && s.rate < 1 && s.t_in > 0) {
+    const double got = 1.0 - std::pow(s.rate, (double)s.t_in);
     s.corr_prev = got > 0 ? s.corr / got : -1.0;
-    s.left = got > 0 ? s.corr_prev - s.corr : -1.0;
+    s.left = s.est_in >= 0 ? s.est_in : (got > 0 ? s.corr_prev - s.corr : -1.0);
   } else {
     s.corr_prev = -1.0;
     s.left = -1.0;
@@ -642,9 +662,11 @@ unsigned scalar_blocks(const lkp_handle *h) {
   return stencil_blocks(h->lattice, (unsigned)h->n[0], (unsigned)h->n[1], (unsigned)h->n[2], h->stile);
 }
 
-// Enqueue a chunk of k >= 1 sweeps whose last sweep reduces norms (and, for
-// k >= 2, compares with the sweep before it).  Updates cur / phi bookkeeping.
-lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
+// Enqueue a chunk of k >= 1 sweeps whose last sweep reduces norms: with
+// `pair` against the Phi of the sweep before it (for k = 1 the Phi stored
+// last), else against the Phi of the previous check in phib[0], writing
+// phib[1] and copying it to phib[0].  Updates cur.
+lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k, bool pair) {
   int cur = h->cur;
   if (h->scalar) {
     for (int j = 0; j < k; ++j) {
@@ -654,11 +676,17 @@ lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
     }
     return LKP_OK;
   }
-  for (int j = 0; j < k - 2; ++j) {
+  const bool two = k >= 2 && pair;
+  for (int j = 0; j < k - (two ? 2 : 1); ++j) {
     if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, 0, nullptr, nullptr)) return st;
     cur = 1 - cur;
   }
-  if (k >= 2) {
+  if (!pair) {
+    if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, FLAG_REDUCE, h->phib[0], h->phib[1]))
+      return st;
+    HIP_TRY(launch_copy_f64(h->phib[1], h->phib[0], h->ncells, s));
+    cur = 1 - cur;
+  } else if (two) {
     if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, FLAG_PHI, nullptr, h->phib[0])) return st;
     cur = 1 - cur;
     if (lkp_status st = enqueue_sweep(h, s, cur, 1 - cur, FLAG_REDUCE, h->phib[0], h->phib[1]))
@@ -673,17 +701,17 @@ lkp_status enqueue_chunk(lkp_handle *h, hipStream_t s, int k) {
   return LKP_OK;
 }
 
-lkp_status run_chunk(lkp_handle *h, int k, bool use_graph) {
+lkp_status run_chunk(lkp_handle *h, int k, bool use_graph, bool pair) {
   if (h->scalar && h->total_sweeps == 0) use_graph = false;  // sweep 1 is a fill
   if (use_graph && k >= 2) {
     // the split is part of the key: a graph launches one split's kernels and
     // its norm finish covers that split's blocks
-    const long key = ((long)k * 2 + h->cur) * 8 + h->split;
+    const long key = (((long)k * 2 + h->cur) * 2 + (pair ? 1 : 0)) * 8 + h->split;
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
       if (!h->capture) HIP_TRY(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
       HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
-      lkp_status st = enqueue_chunk(h, h->capture, k);
+      lkp_status st = enqueue_chunk(h, h->capture, k, pair);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(h->capture, &g);
       if (st) {
@@ -699,9 +727,9 @@ lkp_status run_chunk(lkp_handle *h, int k, bool use_graph) {
     }
     HIP_TRY(hipGraphLaunch(it->second, h->stream));
   } else {
-    if (lkp_status st = enqueue_chunk(h, h->stream, k)) return st;
+    if (lkp_status st = enqueue_chunk(h, h->stream, k, pair)) return st;
   }
-  commit_chunk(h, k);
+  commit_chunk(h, k, pair || h->scalar);
   return LKP_OK;
 }
 
@@ -1336,19 +1364,29 @@ lkp_status lkp_solve(lkp_handle *h, const lkp_solve_opts *o, lkp_solve_report *r
         break;
       }
       const int k = (int)std::min<int64_t>(o->check_every, o->max_sweeps - done);
-      // a one-sweep chunk compares with the previous sweep's Phi only if it exists
+      // The last sweep's change compares with the Phi of the sweep before it
+      // (pair), or, with a relative-L2 tolerance alone, with the Phi stored
+      // before the chunk (the change over the whole interval): a slow mode
+      // whose one-sweep change hides under faster ones still shows over many
+      // sweeps.  span: the sweeps between the two, 0 if no valid Phi exists.
+      const bool pair = !interval_checks(h, *o);
       const int a = h->phi_last;
-      const bool prev_ok = k >= 2 ? (h->total_sweeps + k >= 2)
-                                  : (h->phi_sweep[a] == h->total_sweeps && h->total_sweeps >= 1);
-      if (lkp_status st = run_chunk(h, k, o->use_graph != 0)) return st;
+      int64_t span = 0;
+      if (pair) {
+        span = k >= 2 ? (h->total_sweeps + k >= 2 ? 1 : 0)
+                      : (h->phi_sweep[a] == h->total_sweeps && h->total_sweeps >= 1 ? 1 : 0);
+      } else if (h->phi_sweep[0] >= 0) {
+        span = h->total_sweeps + k - h->phi_sweep[0];
+      }
+      if (lkp_status st = run_chunk(h, k, o->use_graph != 0, pair)) return st;
       double nr[NUM_NORMS];
       if (h->scalar) {
         if (h->total_sweeps < 2) continue;  // the only sweep was the first (Phi = 0)
         if (lkp_status st = read_norms(h, scalar_blocks(h), nr)) return st;
-        result = track_check(h, nr, true, *o, &rep, &converged);
+        result = track_check(h, nr, 1, *o, &rep, &converged);
       } else {
         if (lkp_status st = read_norms(h, sweep_blocks(h, h->split), nr)) return st;
-        result = track_check(h, nr, prev_ok, *o, &rep, &converged);
+        result = track_check(h, nr, span, *o, &rep, &converged);
       }
       if (result) break;
     }

@@ -42,6 +42,7 @@ struct Tracker {
   double rates[kRates] = {0, 0, 0, 0};  // last measured per-sweep contractions
   int nrates = 0;
   int64_t t_prev = -1;
+  int64_t span_prev = 0;        // sweeps between the two Phi the previous check compared
 };
 
 // Iterative-refinement controller state of one F32_IR problem.
@@ -57,6 +58,7 @@ struct IrState {
   double rnorm = -1.0, rnorm_prev = -1.0;
   double corr = 0.0, corr_prev = -1.0;
   double left = -1.0;         // the last correction's own estimate of its remaining error (Phi norm)
+  double est_in = -1.0;       // the running inner solve's latest such estimate
   double est = 1.0;           // estimated relative error of x (1 for x = 0)
   double inner_tol = 1e-4;    // relative accuracy the current inner solve aims at
   int dc = 0;                 // current inner correction buffer
@@ -153,13 +155,19 @@ SweepParams base_params(const lkp_handle *h);
 lkp_status tune_split(lkp_handle *h);
 lkp_status finish_norms(lkp_handle *h, unsigned nblocks, double *dst_dev, hipStream_t s);
 
-// Bookkeeping after a chunk of k sweeps whose last two stored / reduced Phi.
-void commit_chunk(lkp_handle *h, int k);
+// Bookkeeping after a chunk of k sweeps: the last two stored / reduced Phi
+// (pair), or only the last reduced against the Phi stored before the chunk.
+void commit_chunk(lkp_handle *h, int k, bool pair = true);
 
-// Evaluate one check of the plain (F64 / F32) iteration.  prev_ok: the
-// reduced change compares consecutive sweeps.  Sets *converged; returns an
-// error status on divergence.
-lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], bool prev_ok,
+// Whether a plain solve compares Phi across the whole check interval (the
+// K-sweep change) rather than across its last sweep: with a relative-L2
+// tolerance alone, on the population state.
+bool interval_checks(const lkp_handle *h, const lkp_solve_opts &o);
+
+// Evaluate one check of the plain (F64 / F32) iteration.  span: the sweeps
+// between the two Phi the reduced change compares (0: no valid comparison).
+// Sets *converged; returns an error status on divergence.
+lkp_status track_check(lkp_handle *h, const double nr[NUM_NORMS], int64_t span,
                        const lkp_solve_opts &o, lkp_solve_report *rep, bool *converged);
 
 // F32_IR controller, split so that single and batched drivers share it.

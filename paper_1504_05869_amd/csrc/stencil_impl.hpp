@@ -843,8 +843,10 @@ __global__ void __launch_bounds__(256) k_stencil3pa(StencilParams p) {
   constexpr int E = 16 / (int)sizeof(TIN);     // input elements per unit
   constexpr int ES = 16 / (int)sizeof(TSRC);   // source elements per unit
   constexpr int VXA = (VMX + E - 1) / E * E;    // x halo in whole units
-  constexpr int PITCH = TX + 2 * VXA;           // staged input row (elements)
-  constexpr int RU = PITCH / E;                 // units per staged input row
+  // a staged row holds TX + 2 VXA cells and one unit more, so that the two
+  // row groups of a wave (2 CY rows apart) read different LDS banks
+  constexpr int RU = (TX + 2 * VXA) / E + 1;    // units per staged input row
+  constexpr int PITCH = RU * E;                 // staged input row (elements)
   constexpr int LY = TY + 2 * VMY;
   constexpr int XS = VXA - VMX;                 // staged cells left of the halo
   constexpr int NSTEPS = BZ + 2 * VMZ;
@@ -876,7 +878,8 @@ __global__ void __launch_bounds__(256) k_stencil3pa(StencilParams p) {
   TOUT *__restrict__ xout = reinterpret_cast<TOUT *>(p.xout);
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 
-  // input unit u: staged row u / RU, x = x0 - VXA + E (u % RU), rows wrapped
+  // input unit u: staged row u / RU, x = x0 - VXA + E (u % RU), rows and
+  // columns wrapped (the last unit of a row is padding, never read)
   InRows in;
 #pragma unroll
   for (int j = 0; j < NIN; ++j) {

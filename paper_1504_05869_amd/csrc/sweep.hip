@@ -56,6 +56,13 @@ __global__ void k_fill(T *__restrict__ p, T v, size_t n) {
     p[i] = v;
 }
 
+template <class T>
+__global__ void k_copy(const T *__restrict__ src, T *__restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 __global__ void __launch_bounds__(256) k_sum_f32(const float *__restrict__ d, size_t n,
                                                  double *__restrict__ partials,
                                                  const int *__restrict__ opp, unsigned plane) {
@@ -195,6 +202,11 @@ hipError_t launch_f32_to_f64(const float *in, double *out, size_t n, hipStream_t
 
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double *src, double *dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy<double>, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 

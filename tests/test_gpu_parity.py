@@ -121,6 +121,32 @@ def test_converged_f64_matches_spectral(lattice, shape, tau):
     assert rep["est_rel_err"] <= 1e-12
 
 
+@pytest.mark.parametrize("lattice,shape,tau,tol", [("D3Q111", (32, 32, 32), 120.0, 1e-9),
+                                                   ("D2Q81", (64, 64), 300.0, 1e-9),
+                                                   ("D2Q169", (48, 48), 60.0, 1e-9)])
+def test_stopping_estimate_bounds_the_error_when_the_checkerboard_is_slowest(lattice, shape, tau,
+                                                                             tol):
+    """At large tau_lb the N = 5 and N = 7 equilibria (negative phi_i) make the
+    checkerboard mode the slowest, and a source with a checkerboard part puts
+    most of the late error there while faster modes still dominate the
+    one-sweep change.  The estimate, whose contraction never drops below
+    lkp_contraction_bound, still stops at a true error below the tolerance
+    and bounds it, in FP64 and in FP32 + refinement."""
+    blobs = _blobs(shape)
+    sign = np.indices(shape).sum(axis=0) % 2 * 2.0 - 1.0
+    s = W.zero_mean(blobs + 0.5 * sign * np.abs(blobs))
+    ref = SP.fixed_point(lattice, ORDER[lattice], tau, s)
+    for precision in ("f64", "f32_ir"):
+        with lkp.Problem(s, lattice, ORDER[lattice], tau_lb=tau, precision=precision) as p:
+            rep = p.solve(tol_rel_l2=tol, check_every=100, max_sweeps=2000000)
+            phi = p.phi_host()
+        err = rel_l2(phi, ref)
+        say("checkerboard", lattice, precision, "sweeps", rep["sweeps"], "est", rep["est_rel_err"],
+            "true", err, "bound", lkp.contraction_bound(shape, lattice, ORDER[lattice], tau_lb=tau))
+        assert err <= tol
+        assert err <= rep["est_rel_err"] * 1.05
+
+
 def test_config1_stop_rule_matches_oracle():
     """64x64 D2Q5, tau_lb = 1, max|dPhi| < 1e-10 checked every sweep, through
     the population sweep (the tau_lb = 1 stencil form has its own test)."""
