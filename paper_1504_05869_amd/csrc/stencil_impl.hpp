@@ -579,12 +579,15 @@ __device__ __forceinline__ void plane_sums(const TIN *row0, const StencilParams 
 }
 
 // Store a thread's finished output cells (two adjacent x cells on CY rows of
-// plane gz): Phi' = acc + src, or R = acc + src - centre in SMODE_RESID, and
-// on check sweeps add their norms to v.
+// one plane): Phi' = acc + src, or R = acc + src - centre in SMODE_RESID, and
+// on check sweeps add their norms to v.  Cell offsets are 32-bit (grids stay
+// below 2^29 cells): `plane` is the plane's first cell (block-uniform) and
+// `cell0` the thread's first cell within the plane, gy0 nx + gx.
 template <int SM, int FLAGS, int CY, class TC, class TOUT>
 __device__ __forceinline__ void emit_rows(const TC (&acc)[CY][2], const TC (&sv)[CY][2],
-                                          const TC (&cv)[CY][2], bool has_src, TOUT *xout, int gz,
-                                          int gy0, int gx, int nx, int ny, double (&v)[NUM_NORMS]) {
+                                          const TC (&cv)[CY][2], bool has_src, TOUT *xout,
+                                          unsigned plane, unsigned cell0, int gy0, int gx, int nx,
+                                          int ny, double (&v)[NUM_NORMS]) {
   using MT = SModeTraits<SM>;
 #pragma unroll
   for (int k = 0; k < CY; ++k) {
@@ -593,7 +596,7 @@ __device__ __forceinline__ void emit_rows(const TC (&acc)[CY][2], const TC (&sv)
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         if (gx + q < nx) {
-          const size_t c = ((size_t)gz * ny + gy) * nx + gx + q;
+          const unsigned c = cell0 + (plane + (unsigned)(k * nx)) + (unsigned)q;
           TC out = acc[k][q];
           if (has_src) out = out + sv[k][q];
           const TC centre = cv[k][q];
@@ -692,6 +695,7 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
   const int ip = (int)(threadIdx.x % 32);  // cell pair
   const int g = (int)(threadIdx.x / 32);   // row group
   const int gx = x0 + 2 * ip;
+  const unsigned cell0 = (unsigned)((y0 + g * CY) * nx + gx);  // first cell of the thread's rows
   TC acc[NZR][CY][2];
 #pragma unroll
   for (int j = 0; j < NZR; ++j)
@@ -722,6 +726,7 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
         const int m = step - 2 * VMZ;
         const int gz = z0 + m;
         const bool emit = m >= 0 && gz < nz;
+        const unsigned plane = (unsigned)gz * pcells;
         TC sv[CY][2], cv[CY][2];
 #pragma unroll
         for (int k = 0; k < CY; ++k)
@@ -730,7 +735,7 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
             sv[k][q] = cv[k][q] = (TC)0;
             const int gy = y0 + g * CY + k;
             if (emit && gy < ny && gx + q < nx) {
-              const size_t c = ((size_t)gz * ny + gy) * nx + gx + q;
+              const unsigned c = cell0 + (plane + (unsigned)(k * nx)) + (unsigned)q;
               if (src) sv[k][q] = (TC)src[c];
               if constexpr (CENTRE) cv[k][q] = (TC)xin[c];
             }
@@ -763,8 +768,8 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
         // output plane m = step - 2 VMZ is complete
         constexpr int fs = (ph + 1) % NZR;
         if (emit)
-          emit_rows<SM, FLAGS, CY>(acc[fs], sv, cv, src != nullptr, xout, gz, y0 + g * CY, gx, nx, ny,
-                                   v);
+          emit_rows<SM, FLAGS, CY>(acc[fs], sv, cv, src != nullptr, xout, plane, cell0, y0 + g * CY,
+                                   gx, nx, ny, v);
 #pragma unroll
         for (int k = 0; k < CY; ++k) acc[fs][k][0] = acc[fs][k][1] = (TC)0;
       }
@@ -919,6 +924,7 @@ __global__ void __launch_bounds__(256) k_stencil3pa(StencilParams p) {
   const int ip = (int)(threadIdx.x % 32);  // cell pair
   const int g = (int)(threadIdx.x / 32);   // row group
   const int gx = x0 + 2 * ip;
+  const unsigned cell0 = (unsigned)((y0 + g * CY) * nx + gx);  // first cell of the thread's rows
   TC acc[NZR][CY][2];
 #pragma unroll
   for (int j = 0; j < NZR; ++j)
@@ -945,7 +951,8 @@ __global__ void __launch_bounds__(256) k_stencil3pa(StencilParams p) {
           cv[k][1] = (TC)c.b;
         }
       }
-      emit_rows<SM, FLAGS, CY>(acc[slot], sv, cv, has_src, xout, z0 + m, y0 + g * CY, gx, nx, ny, v);
+      emit_rows<SM, FLAGS, CY>(acc[slot], sv, cv, has_src, xout, (unsigned)(z0 + m) * pcells, cell0,
+                               y0 + g * CY, gx, nx, ny, v);
     }
 #pragma unroll
     for (int k = 0; k < CY; ++k) acc[slot][k][0] = acc[slot][k][1] = (TC)0;
