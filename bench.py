@@ -54,11 +54,18 @@ def r_q(lkp, lattice: str) -> int:
 
 def sweep_rate(lkp, torch, s, lattice, order, precision, knudsen=None, tau_lb=None,
                sweeps=200, chunks=1, population_sweep=False, in_place=False, drift=None):
-    """Average duration of one sweep (HIP events on the solver's stream)."""
+    """Average duration of one sweep (HIP events on the solver's stream), timed
+    after about 0.2 s of untimed sweeps on the same problem, so that the GPU's
+    clocks have settled: a few hundred sweeps of a small grid otherwise run
+    while the clocks are still rising."""
     with lkp.Problem(s, lattice, order, knudsen=knudsen, tau_lb=tau_lb, precision=precision,
                      population_sweep=population_sweep, in_place=in_place, drift=drift) as p:
         p.step(2)
         p.sync()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.2:
+            p.step(sweeps)
+            p.sync()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(chunks):
