@@ -601,8 +601,9 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the sweep of a single problem runs on one device).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the sweep of "
+              "a single problem runs on one device; sharding across GPUs is not implemented).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
