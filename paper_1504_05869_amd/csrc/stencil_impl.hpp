@@ -736,7 +736,13 @@ __global__ void __launch_bounds__(256) k_stencil3p(StencilParams p) {
             const int gy = y0 + g * CY + k;
             if (emit && gy < ny && gx + q < nx) {
               const unsigned c = cell0 + (plane + (unsigned)(k * nx)) + (unsigned)q;
-              if (src) sv[k][q] = (TC)src[c];
+              // an FP64 source is read once per sweep: the nontemporal hint
+              // leaves the caches to Phi, whose output the next sweep reads back
+              // (2 % on the FP64 sweep; on 4-byte FP32 loads it cost 15 %)
+              if (src) {
+                if constexpr (sizeof(TSRC) == 8) sv[k][q] = (TC)__builtin_nontemporal_load(src + c);
+                else sv[k][q] = (TC)src[c];
+              }
               if constexpr (CENTRE) cv[k][q] = (TC)xin[c];
             }
           }
